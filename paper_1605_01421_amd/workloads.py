@@ -1,0 +1,343 @@
+"""Seeded synthetic inputs for the SimInf split-step SSA.
+
+This module only builds input data: node populations, parameters, model
+matrices and scheduled-event tables.  It holds none of the method's
+arithmetic, and both the GPU library's tests and the CPU oracle's tests take
+their inputs from here.
+
+Conventions (all 0-based):
+
+* ``u0`` has shape (Nn, Nc): row i is node i's compartment vector, so its
+  C-order flattening is the paper's column-major Nc x Nn ``u0`` (Table 1).
+* ``v0`` (Nn, Nv) and ``ldata`` (Nn, Nld) likewise; ``gdata`` is a vector.
+* ``S`` (Nc, Nt), ``G`` (Nt, Nt), ``E`` (Nc, Ecols), ``N`` (Nc, Ncols) are the
+  paper's matrices (Tables 1 and 2) as dense arrays.
+* ``events`` is a dict of equal-length vectors ``event, time, node, dest, n,
+  proportion, select, shift`` (Table 2) with event codes exit=0, enter=1,
+  intTrans=2, extTrans=3, 0-based nodes / select / shift columns and
+  ``shift = -1`` for "no shift".
+
+The paper's datasets (``nodes``, ``u0_SISe``, ``events_SISe``, ...) are not
+available; the generators below stand in for them with the shapes, sizes and
+distributions of the workloads the library is measured on.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SIR, SIS, SISE, BIRTH_DEATH, IMMIGRATION_DEATH = 0, 1, 2, 3, 4
+EXIT, ENTER, INTTRANS, EXTTRANS = 0, 1, 2, 3
+EVENT_FIELDS = ("event", "time", "node", "dest", "n", "proportion", "select", "shift")
+
+
+def empty_events() -> dict:
+    ev = {k: np.zeros(0, dtype=np.int32) for k in EVENT_FIELDS}
+    ev["proportion"] = np.zeros(0, dtype=np.float64)
+    return ev
+
+
+def make_events(rows) -> dict:
+    """Events from rows (event, time, node, dest, n, proportion, select, shift)."""
+    if len(rows) == 0:
+        return empty_events()
+    cols = list(zip(*rows))
+    ev = {k: np.asarray(c, dtype=np.int32) for k, c in zip(EVENT_FIELDS, cols)}
+    ev["proportion"] = np.asarray(cols[5], dtype=np.float64)
+    return ev
+
+
+def concat_events(*evs) -> dict:
+    return {k: np.concatenate([e[k] for e in evs]) for k in EVENT_FIELDS}
+
+
+@dataclass
+class ModelSpec:
+    model: int
+    S: np.ndarray
+    G: np.ndarray
+    u0: np.ndarray
+    v0: np.ndarray
+    ldata: np.ndarray
+    gdata: np.ndarray
+    tspan: np.ndarray
+    E: np.ndarray
+    N: np.ndarray
+    events: dict = field(default_factory=empty_events)
+    name: str = ""
+
+    @property
+    def Nn(self) -> int:
+        return int(self.u0.shape[0])
+
+    @property
+    def Nc(self) -> int:
+        return int(self.S.shape[0])
+
+    @property
+    def Nv(self) -> int:
+        return int(np.asarray(self.v0).reshape(self.Nn, -1).shape[1]) if self.Nn else 0
+
+    @property
+    def n_days(self) -> int:
+        """Number of unit-time steps: boundaries floor(t0)+1 .. ceil(t_end)."""
+        t0, t1 = float(self.tspan[0]), float(self.tspan[-1])
+        return int(np.ceil(t1) - np.floor(t0)) if t1 > t0 else 0
+
+
+# ---- model matrices ------------------------------------------------------
+
+def sir_matrices():
+    """SIR (eq. SIR): compartments S, I, R; transitions S->I, I->R."""
+    S = np.array([[-1, 0], [1, -1], [0, 1]], dtype=np.int32)
+    G = np.ones((2, 2), dtype=np.int32)
+    # select matrix of the predefined SIR model (columns {S}, {I}, {R}, {S,I,R})
+    E = np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 1]], dtype=np.int32)
+    N = np.zeros((3, 1), dtype=np.int32)
+    return S, G, E, N
+
+
+def sis_matrices():
+    """SIS / SISe: compartments S, I; transitions S->I, I->S (eq. SIRstoich)."""
+    S = np.array([[-1, 1], [1, -1]], dtype=np.int32)
+    G = np.ones((2, 2), dtype=np.int32)
+    E = np.array([[1, 0, 1], [0, 1, 1]], dtype=np.int32)
+    N = np.zeros((2, 1), dtype=np.int32)
+    return S, G, E, N
+
+
+def birth_death_matrices(immigration: bool = False):
+    """One compartment X; transition 0 adds one individual, 1 removes one.
+
+    For immigration-death the first rate is a constant, so no transition
+    makes it stale (G row 0 is empty)."""
+    S = np.array([[1, -1]], dtype=np.int32)
+    G = np.array([[0, 0], [1, 1]] if immigration else [[1, 1], [1, 1]], dtype=np.int32)
+    E = np.array([[1]], dtype=np.int32)
+    N = np.zeros((1, 1), dtype=np.int32)
+    return S, G, E, N
+
+
+def _empty_nodes(Nn, k):
+    return np.zeros((Nn, k), dtype=np.float64)
+
+
+def sir_spec(u0, tspan, beta=0.16, gamma=0.077, events=None, name="SIR") -> ModelSpec:
+    S, G, E, N = sir_matrices()
+    u0 = np.ascontiguousarray(u0, dtype=np.int32).reshape(-1, 3)
+    return ModelSpec(SIR, S, G, u0, _empty_nodes(len(u0), 0), _empty_nodes(len(u0), 0),
+                     np.array([beta, gamma], dtype=np.float64),
+                     np.asarray(tspan, dtype=np.float64), E, N,
+                     events if events is not None else empty_events(), name)
+
+
+def sis_spec(u0, tspan, beta, gamma, events=None, name="SIS") -> ModelSpec:
+    S, G, E, N = sis_matrices()
+    u0 = np.ascontiguousarray(u0, dtype=np.int32).reshape(-1, 2)
+    return ModelSpec(SIS, S, G, u0, _empty_nodes(len(u0), 0), _empty_nodes(len(u0), 0),
+                     np.array([beta, gamma], dtype=np.float64),
+                     np.asarray(tspan, dtype=np.float64), E, N,
+                     events if events is not None else empty_events(), name)
+
+
+def sise_spec(u0, tspan, upsilon, gamma, alpha, beta_q, end_q=(91, 182, 273, 365),
+              phi0=0.0, events=None, name="SISe") -> ModelSpec:
+    """SISe: gdata = (upsilon, gamma, alpha, beta_1..beta_4), ldata per node =
+    the day of year each of the four seasons ends, v = (phi)."""
+    S, G, E, N = sis_matrices()
+    u0 = np.ascontiguousarray(u0, dtype=np.int32).reshape(-1, 2)
+    Nn = len(u0)
+    v0 = np.broadcast_to(np.asarray(phi0, dtype=np.float64).reshape(-1, 1), (Nn, 1)).copy()
+    ld = np.broadcast_to(np.asarray(end_q, dtype=np.float64), (Nn, 4)).copy()
+    gd = np.array([upsilon, gamma, alpha, *beta_q], dtype=np.float64)
+    return ModelSpec(SISE, S, G, u0, v0, ld, gd, np.asarray(tspan, dtype=np.float64),
+                     E, N, events if events is not None else empty_events(), name)
+
+
+def birth_death_spec(x0, tspan, b, d, immigration=False, name=None) -> ModelSpec:
+    S, G, E, N = birth_death_matrices(immigration)
+    u0 = np.ascontiguousarray(x0, dtype=np.int32).reshape(-1, 1)
+    return ModelSpec(IMMIGRATION_DEATH if immigration else BIRTH_DEATH, S, G, u0,
+                     _empty_nodes(len(u0), 0), _empty_nodes(len(u0), 0),
+                     np.array([b, d], dtype=np.float64),
+                     np.asarray(tspan, dtype=np.float64), E, N, empty_events(),
+                     name or ("immigration-death" if immigration else "birth-death"))
+
+
+# ---- the paper's small examples -----------------------------------------
+
+def sir_first_example(n=1000):
+    """Section 4.1.1: n nodes of (999, 1, 0), tspan = 1, 8, ..., 176."""
+    u0 = np.tile(np.array([999, 1, 0], dtype=np.int32), (n, 1))
+    return sir_spec(u0, np.arange(1, 181, 7), 0.16, 0.077, name="sir-first-example")
+
+
+def sir_event_example(infect=True):
+    """Section 4.1.2: five empty nodes; enters on days 1-10 (node k gets k
+    susceptibles per day), optionally one infected into node 5 on day 25,
+    eleven moves of 5 individuals on days 35-45, 20% exits on days 70, 110."""
+    rows = []
+    for t in range(1, 11):
+        for k in range(1, 6):
+            rows.append((ENTER, t, k - 1, 0, k, 0.0, 0, -1))
+    if infect:
+        rows.append((ENTER, 25, 4, 0, 1, 0.0, 1, -1))
+    src = [5, 5, 5, 5, 4, 4, 4, 3, 3, 2, 1]
+    dst = [4, 3, 3, 1, 3, 2, 1, 2, 1, 1, 2]
+    for t, a, b in zip(range(35, 46), src, dst):
+        rows.append((EXTTRANS, t, a - 1, b - 1, 5, 0.0, 3, -1))
+    for k in range(1, 6):
+        for t in (70, 110):
+            rows.append((EXIT, t, k - 1, 0, 0, 0.2, 3, -1))
+    u0 = np.zeros((5, 3), dtype=np.int32)
+    return sir_spec(u0, np.arange(1, 181), 0.16, 0.077, events=make_events(rows),
+                    name="sir-event-example")
+
+
+# ---- benchmark workloads --------------------------------------------------
+
+def config0() -> ModelSpec:
+    """Plain SIR: 100 nodes of (990, 10, 0), beta 0.16, gamma 0.077, tspan 1..100."""
+    u0 = np.tile(np.array([990, 10, 0], dtype=np.int32), (100, 1))
+    return sir_spec(u0, np.arange(1, 101), 0.16, 0.077, name="sir-100-plain")
+
+
+def _demographic_events(rng, Nn, tot, days, birth, exit_, ship_frac, select_all,
+                        birth_select, geom_p=0.2, pareto_a=1.2):
+    """Daily births (enter), exits and external transfers for Nn nodes.
+
+    births ~ Poisson(birth * N_i) into the compartment of ``birth_select``;
+    exits ~ Binomial(N_i, exit_) over all compartments; each day a fraction
+    ``ship_frac`` of the nodes ship Geometric(geom_p) individuals to a
+    destination drawn with probability proportional to Pareto(pareto_a)
+    weights (preferential attachment), never to themselves.  The generator
+    follows each node's total through the same-day order exit < enter <
+    external transfer, so no event asks for more individuals than exist.
+    """
+    tot = tot.astype(np.int64).copy()
+    w = rng.pareto(pareto_a, Nn) + 1.0
+    cw = np.cumsum(w) / w.sum()
+    out = {k: [] for k in EVENT_FIELDS}
+
+    def add(kind, t, node, dest, n, sel):
+        m = len(node)
+        out["event"].append(np.full(m, kind, np.int32))
+        out["time"].append(np.full(m, t, np.int32))
+        out["node"].append(node.astype(np.int32))
+        out["dest"].append(dest.astype(np.int32))
+        out["n"].append(n.astype(np.int32))
+        out["proportion"].append(np.zeros(m, np.float64))
+        out["select"].append(np.full(m, sel, np.int32))
+        out["shift"].append(np.full(m, -1, np.int32))
+
+    idx = np.arange(Nn)
+    for t in range(1, days + 1):
+        ex = rng.binomial(tot, exit_)
+        ex = np.minimum(ex, tot)
+        sel = ex > 0
+        add(EXIT, t, idx[sel], np.zeros(sel.sum()), ex[sel], select_all)
+        tot -= ex
+        bi = rng.poisson(birth * tot)
+        sel = bi > 0
+        add(ENTER, t, idx[sel], np.zeros(sel.sum()), bi[sel], birth_select)
+        tot += bi
+        k = rng.binomial(Nn, ship_frac)
+        if k:
+            srcs = rng.choice(Nn, size=k, replace=False)
+            dsts = np.searchsorted(cw, rng.random(k), side="right").clip(0, Nn - 1)
+            same = dsts == srcs
+            while same.any():
+                dsts[same] = np.searchsorted(cw, rng.random(same.sum()), side="right").clip(0, Nn - 1)
+                same = dsts == srcs
+            n = rng.geometric(geom_p, size=k).astype(np.int64)
+            ns = np.zeros(k, np.int64)
+            for j in range(k):  # sequential: a destination may ship later the same day
+                a, b_ = srcs[j], dsts[j]
+                ns[j] = min(n[j], tot[a])
+                tot[a] -= ns[j]
+                tot[b_] += ns[j]
+            keep = ns > 0
+            add(EXTTRANS, t, srcs[keep], dsts[keep], ns[keep], select_all)
+    return {k: np.concatenate(v) if v else np.zeros(0) for k, v in out.items()}
+
+
+def config1(seed: int = 1, Nn: int = 10_000, days: int = 365) -> ModelSpec:
+    """SIR with scheduled events: lognormal node sizes (median 100, sigma 1,
+    clipped to 1..5000), 1% infected, daily births Poisson(0.0005 N) into S,
+    exits Binomial(N, 0.0003) over S/I/R, 0.5% of the nodes ship a
+    Geometric(mean 5) batch per day to Pareto-weighted destinations."""
+    rng = np.random.default_rng(seed)
+    size = np.clip(np.round(rng.lognormal(np.log(100.0), 1.0, Nn)), 1, 5000).astype(np.int64)
+    I0 = np.round(0.01 * size).astype(np.int64)
+    u0 = np.stack([size - I0, I0, np.zeros(Nn, np.int64)], axis=1).astype(np.int32)
+    ev = _demographic_events(rng, Nn, size, days, birth=0.0005, exit_=0.0003,
+                             ship_frac=0.005, select_all=3, birth_select=0)
+    return sir_spec(u0, np.arange(0, days + 1), 0.16, 0.077, events=ev,
+                    name=f"sir-events-{Nn}x{days}")
+
+
+def config2(seed: int = 2, Nn: int = 37_000, days: int = 3650) -> ModelSpec:
+    """SISe with events: lognormal sizes (median 40, sigma 0.39, about 1.6M
+    individuals for 37,000 nodes), 10% of nodes start with floor(5% of S)
+    infected, phi0 = 0, upsilon 0.0175, gamma 0.1, alpha 1, quarterly decay
+    (0.1, 0.12, 0.1, 0.11); births and exits at 0.0009 per individual-day
+    and 0.5% of nodes shipping per day (about 1e6 events per simulated year
+    at full size)."""
+    rng = np.random.default_rng(seed)
+    size = np.maximum(np.round(rng.lognormal(np.log(40.0), 0.39, Nn)), 1).astype(np.int64)
+    I0 = np.zeros(Nn, np.int64)
+    inf = rng.choice(Nn, size=max(1, Nn // 10), replace=False)
+    I0[inf] = np.floor(0.05 * size[inf]).astype(np.int64)
+    u0 = np.stack([size - I0, I0], axis=1).astype(np.int32)
+    ev = _demographic_events(rng, Nn, size, days, birth=0.0009, exit_=0.0009,
+                             ship_frac=0.005, select_all=2, birth_select=0)
+    return sise_spec(u0, np.arange(0, days + 1), 0.0175, 0.1, 1.0,
+                     (0.1, 0.12, 0.1, 0.11), events=ev, name=f"sise-events-{Nn}x{days}")
+
+
+@dataclass
+class EnsembleSet:
+    spec: ModelSpec
+    replicates: int
+    features: np.ndarray  # surrogate inputs (8,)
+
+
+def ensemble_sets(seed: int = 3, n_sets: int = 64, replicates: int = 64, days: int = 365,
+                  nn_range=(100, 20_000), record_every: int = 7) -> list:
+    """Batched-ensemble parameter sets: half SIR (beta in U[0.08, 0.24],
+    gamma in U[0.0385, 0.1155]), half SISe (upsilon in U[0.00875, 0.02625],
+    gamma in U[0.05, 0.15]); per set a node count log-uniform on nn_range,
+    lognormal node sizes (median log-uniform on [20, 1000], sigma in
+    U[0.3, 1.0]) and an initial prevalence in U[0.001, 0.05]; no scheduled
+    events; state recorded every ``record_every`` days."""
+    rng = np.random.default_rng(seed)
+    sets = []
+    tspan = np.arange(0, days + 1, record_every, dtype=np.float64)
+    if tspan[-1] != days:
+        tspan = np.append(tspan, float(days))
+    for k in range(n_sets):
+        sise = k >= n_sets // 2
+        Nn = int(np.floor(np.exp(rng.uniform(np.log(nn_range[0]), np.log(nn_range[1])))))
+        med = float(np.exp(rng.uniform(np.log(20.0), np.log(1000.0))))
+        sig = float(rng.uniform(0.3, 1.0))
+        size = np.maximum(np.round(rng.lognormal(np.log(med), sig, Nn)), 1).astype(np.int64)
+        prev = float(rng.uniform(0.001, 0.05))
+        I0 = rng.binomial(size, prev)
+        gamma = float(rng.uniform(0.05, 0.15) if sise else rng.uniform(0.0385, 0.1155))
+        if sise:
+            ups = float(rng.uniform(0.00875, 0.02625))
+            u0 = np.stack([size - I0, I0], axis=1).astype(np.int32)
+            spec = sise_spec(u0, tspan, ups, gamma, 1.0, (0.1, 0.12, 0.1, 0.11),
+                             name=f"set{k}-sise")
+            par = (1.0, 0.0, ups)
+        else:
+            beta = float(rng.uniform(0.08, 0.24))
+            u0 = np.stack([size - I0, I0, np.zeros(Nn, np.int64)], axis=1).astype(np.int32)
+            spec = sir_spec(u0, tspan, beta, gamma, name=f"set{k}-sir")
+            par = (0.0, beta, 0.0)
+        ls = np.log(size.astype(np.float64))
+        feats = np.array([par[0], par[1], par[2], gamma, I0.sum() / size.sum(),
+                          ls.mean(), ls.var(), np.log(Nn)], dtype=np.float64)
+        sets.append(EnsembleSet(spec, replicates, feats))
+    return sets
