@@ -1,0 +1,218 @@
+/*
+ * siminf.h -- C ABI of libsiminf.so, an MI355X (gfx950) implementation of
+ * the split-step stochastic simulation of Widgren, Bauer, Eriksson &
+ * Engblom, "SimInf: An R package for data-driven stochastic disease spread
+ * simulations" (arXiv 1605.01421).
+ *
+ * What a run computes (section 2.3, eqs. numstep1-numstep3; Appendix A):
+ * every node (sub-population) i holds an integer compartment vector u[,i]
+ * (and optionally a real vector v[,i]).  Time advances one unit ("day") at a
+ * time.  Within a day each node runs Gillespie's direct method: sum of the
+ * transition rates lambda, waiting time tau = -log(r1)/lambda, stop when the
+ * next transition would pass the day boundary, otherwise pick transition n
+ * by inversion with r2, add column S[,n] to u[,i] and recompute the rates
+ * that the dependency graph G marks.  At the boundary the node's scheduled
+ * exit / enter / internal-transfer events (E1) are applied, then -- after
+ * all nodes reached the boundary -- the external transfers (E2) in table
+ * order, then the post-time-step function updates v[,i] (section 3.4).
+ * U and V are recorded whenever time passes a tspan point (Table 1).
+ *
+ * Random numbers are Philox4x32-10 blocks (Salmon et al., SC'11) used as a
+ * keyed counter function: key = seed; SSA step k of node i (0-based within
+ * its run) while advancing towards integer day T uses counter
+ * (k, (uint32)T, i, stream & 0xFFFFFF); event sampling of the event with
+ * input index e uses counters (b, 0, e, (stream & 0xFFFFFF) | 1<<24) for
+ * blocks b = 0, 1, ...  Results therefore do not depend on the launch shape.
+ * Uniforms: r = (k + 1/2) 2^-52 with k = (w_a << 20) | (w_b >> 12); r1 from
+ * words 0,1 and r2 from words 2,3 of the step's block.  log(r1) is the
+ * library's own series logarithm (reduction of the argument to
+ * [sqrt(1/2), sqrt(2)] times a power of two, the atanh series up to s^23,
+ * ln 2 in two parts), every operation one IEEE binary64 rounding.  Sampling
+ * without replacement draws one individual at a time with Lemire's unbiased
+ * bounded integer on successive 32-bit words.
+ *
+ * Conventions: every function returns an int status, 0 on success and one
+ * of the negative SIMINF_E_* codes otherwise; none aborts the process.
+ * Indices are 0-based; shift = -1 means "no shift".  Matrices are dense and
+ * column-major as in the paper (S is Nc x Nt, element (c, j) at S[c + j*Nc];
+ * u0 is Nc x Nn, node i's compartments at u0[c + i*Nc]).  A handle is used
+ * by one host thread at a time; separate handles are independent.
+ */
+#ifndef SIMINF_H
+#define SIMINF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------- */
+enum {
+    SIMINF_OK = 0,
+    SIMINF_E_ARG = -1,            /* invalid argument or model (validity check, section 3.4.2) */
+    SIMINF_E_UNSUPPORTED = -2,    /* model id or size outside what the library implements */
+    SIMINF_E_ALLOC = -3,          /* device or host allocation failed */
+    SIMINF_E_DEVICE = -4,         /* HIP runtime error, or an in-kernel barrier timed out */
+    SIMINF_E_NEG_STATE = -5,      /* a transition made a compartment negative (App. A, 17) */
+    SIMINF_E_BAD_RATE = -6,       /* a transition rate was negative or not finite */
+    SIMINF_E_EVENT_OVERDRAW = -7, /* an event asked for more individuals than exist (sec. 4.1.2) */
+    SIMINF_E_EVENT_INDEX = -8,    /* an event names a node / select / shift out of range */
+    SIMINF_E_PTS = -9             /* the post-time-step function failed (non-finite state) */
+};
+
+/* ---- built-in models (the TRFun / PTSFun pairs of section 3.4.1) ----------
+ * SIR (eq. SIR): Nc=3 (S,I,R), Nt=2, gdata=(beta, gamma), Nv=0, Nld=0.
+ *    S->I at beta*S*I/(S+I+R) (0 when the node is empty), I->R at gamma*I.
+ * SIS (eqs. sirtrans, SIRstoich): Nc=2, Nt=2, gdata=(beta, gamma).
+ *    S+I->2I at beta*S*I, I->S at gamma*I.
+ * SISE (sec. 4.2 without spatial coupling): Nc=2, Nt=2, Nv=1 (phi),
+ *    Nld=4 (day of year each season ends), gdata=(upsilon, gamma, alpha,
+ *    beta_1..beta_4).  S->I at upsilon*phi*S, I->S at gamma*I; after each day
+ *    phi <- phi*(1-beta_q) + alpha*I/(S+I) (0 for an empty node), q = first
+ *    season whose end is >= the day of year of the new day (else season 1).
+ * BIRTH_DEATH: Nc=1, Nt=2, gdata=(b, d): X->2X at b*X, X->0 at d*X.
+ * IMMIGRATION_DEATH: Nc=1, Nt=2, gdata=(kappa, mu): 0->X at kappa, X->0 at mu*X.
+ * Arithmetic is IEEE binary64 in the operation order written above. */
+enum {
+    SIMINF_SIR = 0,
+    SIMINF_SIS = 1,
+    SIMINF_SISE = 2,
+    SIMINF_BIRTH_DEATH = 3,
+    SIMINF_IMMIGRATION_DEATH = 4
+};
+
+/* event type codes (Table 2) */
+enum { SIMINF_EXIT = 0, SIMINF_ENTER = 1, SIMINF_INTTRANS = 2, SIMINF_EXTTRANS = 3 };
+
+/* what a run records at each tspan point */
+enum {
+    SIMINF_RECORD_FULL = 0, /* U (and V) for every node: siminf_trajectory */
+    SIMINF_RECORD_SUMS = 1  /* per run, the sum over nodes of each compartment: siminf_sums */
+};
+
+/* One model run's inputs (Tables 1 and 2).  All pointers are host memory
+ * owned by the caller; siminf_create copies them and keeps no reference.
+ *   S      Nc x Nt  state-change matrix (column j added when transition j fires)
+ *   G      Nt x Nt  dependency graph: G[k + j*Nt] != 0 means rate k is
+ *                   recomputed after transition j
+ *   u0     Nc x Nn  initial compartments (>= 0)
+ *   v0     Nv x Nn  initial continuous state
+ *   ldata  Nld x Nn local data;  gdata  Ngd global data
+ *   tspan  Ntspan strictly increasing output times; tspan[0] is the start,
+ *          tspan[Ntspan-1] the end.  Time advances in unit steps to the
+ *          integer days floor(tspan[0])+1, ..., ceil(tspan[Ntspan-1]).
+ *   events Nev rows: ev_type (SIMINF_EXIT..EXTTRANS), ev_time (integer day;
+ *          an event is applied at the first day boundary T >= ev_time, so
+ *          events at or before tspan[0] are applied at the first boundary),
+ *          ev_node, ev_dest (external transfers only), ev_n (>= 0; 0 means
+ *          round(ev_prop * selected total), half away from zero), ev_prop in
+ *          [0, 1], ev_select (column of E), ev_shift (column of N, or -1).
+ *   E      Nc x Ecols select matrix; N  Nc x Ncols shift matrix (Table 2).
+ * Same-day order: exit < enter < internal transfer (per node, in the
+ * node's own lane) < external transfer (all nodes, in input order). */
+typedef struct {
+    int32_t model, Nc, Nt, Nn, Nv, Nld, Ngd, Ntspan;
+    const int32_t *S, *G, *u0;
+    const double *v0, *ldata, *gdata, *tspan;
+    int32_t Nev, Ecols, Ncols;
+    const int32_t *ev_type, *ev_time, *ev_node, *ev_dest, *ev_n, *ev_select, *ev_shift;
+    const double *ev_prop;
+    const int32_t *E, *N;
+} siminf_spec;
+
+/* Launch and recording options; a zeroed struct (or NULL) gives defaults. */
+typedef struct {
+    int32_t record;    /* SIMINF_RECORD_FULL (default) or SIMINF_RECORD_SUMS */
+    int32_t block;     /* threads per workgroup, multiple of 64 up to 1024; 0 = tuned */
+    int32_t order;     /* lane order: 0 = binned by expected work (default), 1 = input order */
+    int32_t lanes;     /* lanes cooperating on one node: 1 (default), 2, 4 or 8 */
+    int32_t max_blocks;/* cap on the number of workgroups (0 = occupancy limit) */
+    int32_t reserved[3];
+} siminf_options;
+
+typedef struct siminf_model siminf_model;
+
+/* Validates one run (the validity check of section 3.4.2), copies it to
+ * device memory of the current HIP device and returns a handle in *out.
+ * Static event errors are reported here: SIMINF_E_EVENT_INDEX for a node,
+ * dest, select or shift out of range (also a shift target outside 0..Nc-1
+ * for any selected compartment); siminf_error_info then names the event.
+ * Limits: Nc <= 16, Nt <= 32, Ecols <= 1<<20, Ntspan >= 1, Nn >= 0. */
+int siminf_create(const siminf_spec *spec, const siminf_options *opt, siminf_model **out);
+
+/* A batch: specs[s] is run replicates[s] times (run r of the batch uses
+ * stream_base + r in siminf_run; runs are numbered spec by spec).  All specs
+ * share tspan; specs of the same model must share S, G, E and N.  External
+ * transfers are allowed only when every spec is the same model.  Each run's
+ * results equal a single-run siminf_create/siminf_run of that spec with
+ * stream = stream_base + r. */
+int siminf_create_batch(const siminf_spec *specs, int32_t nspecs, const int32_t *replicates,
+                        const siminf_options *opt, siminf_model **out);
+
+/* Enqueues one complete run (all days, events, post-time steps and
+ * records) on hip_stream (a hipStream_t; NULL = the null stream) and
+ * returns without waiting.  Runs of the same handle must not overlap.
+ * seed is the Philox key; stream_base < 2^24 - (number of runs). */
+int siminf_run(siminf_model *m, uint64_t seed, uint32_t stream_base, void *hip_stream);
+
+/* Waits for the last run and returns its status: 0 or the code of the first
+ * error in the serial order (day, phase SSA < E1 < E2 < PTS, node or event
+ * index), as siminf_error_info reports. */
+int siminf_wait(siminf_model *m);
+
+/* Copies run `run`'s recorded U (Nc*Nn x Ntspan, column-major: node i's
+ * compartment c at tspan[k] is U[c + i*Nc + k*Nc*Nn]) and V (Nv*Nn x
+ * Ntspan, same layout) to U / V (either may be NULL).  dst_is_device != 0
+ * means U and V are device pointers on the model's device.  Waits for the
+ * last run.  Requires SIMINF_RECORD_FULL. */
+int siminf_trajectory(siminf_model *m, int32_t run, int32_t *U, double *V, int32_t dst_is_device);
+
+/* Copies the per-run compartment sums, int64 [runs][Ntspan][Nc] row-major,
+ * to sums (host, or device if dst_is_device).  Requires SIMINF_RECORD_SUMS. */
+int siminf_sums(siminf_model *m, int64_t *sums, int32_t dst_is_device);
+
+/* Counters of the last run: out[0] transitions executed, out[1] node-days
+ * simulated, out[2] scheduled events applied.  Waits for the last run. */
+int siminf_counters(siminf_model *m, uint64_t out[3]);
+
+/* Sizes of a handle: out[0] runs, out[1] total nodes, out[2] Ntspan,
+ * out[3] Nc (largest over specs), out[4] Nv (largest), out[5] day steps. */
+int siminf_shape(const siminf_model *m, int64_t out[6]);
+
+/* First error of the last run (or of create): code, 0-based day step,
+ * phase (0 SSA, 1 E1, 2 E2, 3 PTS; -1 = create), index (node within its
+ * run for SSA/PTS, event input index for events) and run. */
+int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32_t *phase,
+                      int64_t *index, int32_t *run);
+
+/* Launch configuration chosen for the handle: out[0] threads per block,
+ * out[1] blocks, out[2] mode (0 free-running, 1 day-synchronous),
+ * out[3] lanes per node, out[4] order. */
+int siminf_launch_info(const siminf_model *m, int32_t out[5]);
+
+/* Frees the handle and its device memory (waits for its last run). */
+void siminf_destroy(siminf_model *m);
+
+/* Status code name, e.g. "SIMINF_E_EVENT_OVERDRAW". */
+const char *siminf_status_string(int32_t code);
+
+/* ---- prevalence and quantiles (section 4.2, prevalence(); surrogate targets)
+ * For a SIMINF_RECORD_SUMS batch whose runs are grouped in sets of
+ * `replicates` consecutive runs: population prevalence
+ *     P[r][k] = sums[r][k][case_c] / sum_{c in at_risk} sums[r][k][c]
+ * (0 when the denominator is 0) for the tspan indices k = k0, k0+1, ...,
+ * k0+nk-1, then for every set and k the type-7 quantiles (linear
+ * interpolation between order statistics, h = (R-1) p) at the nq
+ * probabilities `probs`, written as float out[set][k-k0][q] (device
+ * pointer).  at_risk_mask has bit c set for each compartment in the
+ * denominator.  Computed in binary64 and rounded once to float. */
+int siminf_prevalence_quantiles(siminf_model *m, int32_t case_c, uint32_t at_risk_mask,
+                                int32_t replicates, int32_t k0, int32_t nk,
+                                const double *probs, int32_t nq, float *out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMINF_H */

@@ -1,0 +1,111 @@
+// internal.h -- structures shared by the host runtime (runtime.cpp) and the
+// kernels (ssa_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace siminf {
+
+constexpr int MAX_NC = 4;     // largest compartment count of the built-in models
+constexpr int MAX_NT = 2;     // every built-in model has two transitions
+constexpr int WAVE = 64;      // gfx950 wavefront
+constexpr int MAX_GROUPS = 8; // one group per built-in model present in a batch
+
+// phases of one unit of time, in the order of Appendix A
+enum Phase { PH_SSA = 0, PH_E1 = 1, PH_E2 = 2, PH_PTS = 3 };
+
+// Error key: ordered like the serial algorithm (step, phase, global ordinal),
+// code in the low bits.  The global ordinal of a node is its input position
+// across runs; of an event, its position in the concatenated event tables.
+__host__ __device__ inline uint64_t make_err_key(uint32_t step, uint32_t phase, uint64_t ordinal,
+                                                 uint32_t code) {
+    return ((uint64_t)step << 44) | ((uint64_t)(phase & 3u) << 42) |
+           ((ordinal & ((1ull << 38) - 1)) << 4) | (code & 0xFu);
+}
+constexpr uint64_t NO_ERROR = ~0ull;
+constexpr uint32_t MAX_STEPS = 1u << 20;
+constexpr uint64_t MAX_ORDINAL = 1ull << 38;
+
+// Per-run control block in device memory, reset before each run.
+struct Ctrl {
+    unsigned long long err_key;
+    unsigned long long counters[3];  // transitions, node-days, events
+    unsigned int work[MAX_GROUPS];   // work-queue cursors (free-running mode)
+    unsigned int bar_count;          // grid barrier arrivals
+    unsigned int bar_gen;            // grid barrier generation (never reset)
+    unsigned int abort;              // set when a barrier wait timed out
+    unsigned int pad;
+};
+
+// Scheduled events, structure of arrays, sorted for their consumer.
+struct EventSoA {
+    const int32_t* time;
+    const int32_t* type;
+    const int32_t* n;
+    const int32_t* select;
+    const int32_t* shift;
+    const int32_t* id;       // input index within its spec (RNG identity)
+    const int64_t* ordinal;  // global ordinal for the error key
+    const double* prop;
+    const int32_t* node;     // group-local node of the event (E2: source)
+    const int32_t* dest;     // group-local destination (E2 only)
+};
+
+struct KParams {
+    int32_t n;        // nodes in the group
+    int32_t nb;       // number of unit-time steps
+    int32_t ntspan;
+    int32_t mode;     // 0 free-running, 1 day-synchronous
+    int64_t T1;       // first day boundary
+    double t0;        // start time
+    uint64_t seed;
+    uint32_t stream_base;
+    int32_t ngd;
+    int32_t S[MAX_NC * MAX_NT];  // state-change matrix, column-major
+    uint32_t Gmask[MAX_NT];      // bit k of Gmask[j]: recompute rate k after transition j
+    int32_t ecols, ncols;
+    const uint32_t* Emask;       // [ecols] bit c: compartment c selected
+    const int32_t* Nshift;       // [ncols][MAX_NC]
+    const int32_t* rec_off;      // [nb+1] tspan indices written after step b
+    const int32_t* u0;           // [nc][n]
+    const double* v0;            // [nv][n]
+    int32_t* u;                  // live state [nc][n] (day-synchronous mode)
+    double* v;                   // [nv][n]
+    const double* ld;            // [nld][n]
+    const int32_t* node_run;     // [n] run of each node
+    const int32_t* node_idx;     // [n] node index within its run
+    const int64_t* node_ord;     // [n] global input ordinal
+    const double* gdata;         // [nspec][ngd]
+    const int32_t* run_spec;     // [runs]
+    const int32_t* e1_off;       // [n+1]
+    int32_t* e1_cur;             // [n]
+    EventSoA e1;
+    const int32_t* e2_step;      // [nb+1] level range of each step
+    const int32_t* e2_lvl;       // [levels+1] event range of each level
+    EventSoA e2;
+    int32_t record;              // 0 full, 1 sums
+    int32_t sums_nc;             // compartment stride of the sums array
+    int32_t* U;                  // [ntspan][nc][n]
+    double* V;                   // [ntspan][nv][n]
+    unsigned long long* sums;    // [runs][ntspan][sums_nc]
+    Ctrl* ctrl;
+    int32_t group;
+    int32_t nchunks;             // 64-node chunks (free-running work queue)
+    int32_t nblocks;
+    int32_t pad;
+};
+
+// Launchers implemented in ssa_kernels.hip.
+hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
+                       const unsigned long long* sums_init, long long sums_len, hipStream_t st);
+hipError_t launch_group(int model, const KParams& p, int block, int blocks, bool cooperative,
+                        hipStream_t st);
+int max_blocks_per_cu(int model, int mode, int block);
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n,
+                         int ntspan, const int32_t* pos, int nn, int32_t* Uo, double* Vo,
+                         hipStream_t st);
+hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,
+                             int case_c, uint32_t mask, int reps, int k0, int nk,
+                             const double* probs, int nq, float* out, hipStream_t st);
+
+}  // namespace siminf

@@ -1,0 +1,133 @@
+// models.h -- built-in transition-rate and post-time-step functions, one
+// functor per model (the TRFun / PTSFun pairs of section 3.4.1).  Device code
+// cannot call host function pointers, so each model is a compile-time type
+// and the kernels are instantiated per model.  Operation order is normative:
+// the results must be bit-identical to any other implementation following
+// the same formulas in IEEE binary64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace siminf {
+
+enum ModelId { M_SIR = 0, M_SIS = 1, M_SISE = 2, M_BIRTH_DEATH = 3, M_IMMIGRATION_DEATH = 4 };
+
+// SIR (eq. SIR): S -> I at beta S I / (S + I + R), 0 for an empty node
+// (Appendix C listing); I -> R at gamma I.  gdata = (beta, gamma).
+struct ModelSIR {
+    static constexpr int ID = M_SIR, NC = 3, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    template <int J>
+    __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
+                                                  const double* gd) {
+        if constexpr (J == 0) {
+            const double s = (double)u[0], i = (double)u[1], r = (double)u[2];
+            const double n = (s + i) + r;
+            return n > 0.0 ? ((gd[0] * s) * i) / n : 0.0;
+        } else {
+            return gd[1] * (double)u[1];
+        }
+    }
+    __device__ static __forceinline__ bool pts(double*, const int32_t*, const double*, const double*,
+                                               int64_t) {
+        return true;
+    }
+};
+
+// SIS (eqs. sirtrans, SIRstoich): S + I -> 2I at beta S I; I -> S at gamma I.
+struct ModelSIS {
+    static constexpr int ID = M_SIS, NC = 2, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    template <int J>
+    __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
+                                                  const double* gd) {
+        if constexpr (J == 0)
+            return (gd[0] * (double)u[0]) * (double)u[1];
+        else
+            return gd[1] * (double)u[1];
+    }
+    __device__ static __forceinline__ bool pts(double*, const int32_t*, const double*, const double*,
+                                               int64_t) {
+        return true;
+    }
+};
+
+// SISe (section 4.2 without the spatial coupling term): S -> I at upsilon phi
+// per susceptible, I -> S at gamma per infected.  After every unit of time
+// phi is advanced by one explicit-Euler step of length 1 of
+// d phi/dt = alpha I/N - beta(t) phi (eq. numstep3):
+//   phi <- phi (1 - beta_q) + alpha I / N,  N = S + I (the I/N term is 0 if N = 0)
+// with season q the first of the four whose end day-of-year (ldata) is >= the
+// day of year of the new day, else the first season.
+// gdata = (upsilon, gamma, alpha, beta_1, beta_2, beta_3, beta_4).
+struct ModelSISe {
+    static constexpr int ID = M_SISE, NC = 2, NT = 2, NV = 1, NLD = 4, NGD = 7;
+    template <int J>
+    __device__ static __forceinline__ double rate(const int32_t* u, const double* v, const double*,
+                                                  const double* gd) {
+        if constexpr (J == 0)
+            return (gd[0] * v[0]) * (double)u[0];
+        else
+            return gd[1] * (double)u[1];
+    }
+    __device__ static __forceinline__ bool pts(double* v, const int32_t* u, const double* ld,
+                                               const double* gd, int64_t day) {
+        int64_t r = (day - 1) % 365;
+        if (r < 0) r += 365;
+        const double doy = (double)(r + 1);
+        const double decay = doy <= ld[0] ? gd[3] : doy <= ld[1] ? gd[4]
+                           : doy <= ld[2] ? gd[5] : doy <= ld[3] ? gd[6] : gd[3];
+        const double kept = v[0] * (1.0 - decay);
+        const int32_t total = u[0] + u[1];
+        const double shed = total > 0 ? (gd[2] * (double)u[1]) / (double)total : 0.0;
+        const double phi = kept + shed;
+        v[0] = phi;
+        return isfinite(phi);
+    }
+};
+
+// Linear birth-death: X -> 2X at b X, X -> 0 at d X.  gdata = (b, d).
+struct ModelBirthDeath {
+    static constexpr int ID = M_BIRTH_DEATH, NC = 1, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    template <int J>
+    __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
+                                                  const double* gd) {
+        return gd[J] * (double)u[0];
+    }
+    __device__ static __forceinline__ bool pts(double*, const int32_t*, const double*, const double*,
+                                               int64_t) {
+        return true;
+    }
+};
+
+// Immigration-death: 0 -> X at kappa, X -> 0 at mu X.  gdata = (kappa, mu).
+struct ModelImmigrationDeath {
+    static constexpr int ID = M_IMMIGRATION_DEATH, NC = 1, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    template <int J>
+    __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
+                                                  const double* gd) {
+        if constexpr (J == 0)
+            return gd[0];
+        else
+            return gd[1] * (double)u[0];
+    }
+    __device__ static __forceinline__ bool pts(double*, const int32_t*, const double*, const double*,
+                                               int64_t) {
+        return true;
+    }
+};
+
+// Host-side table of model shapes.
+struct ModelShape {
+    int nc, nt, nv, nld, ngd;
+};
+inline bool model_shape(int id, ModelShape* s) {
+    switch (id) {
+        case M_SIR: *s = {3, 2, 0, 0, 2}; return true;
+        case M_SIS: *s = {2, 2, 0, 0, 2}; return true;
+        case M_SISE: *s = {2, 2, 1, 4, 7}; return true;
+        case M_BIRTH_DEATH: *s = {1, 2, 0, 0, 2}; return true;
+        case M_IMMIGRATION_DEATH: *s = {1, 2, 0, 0, 2}; return true;
+    }
+    return false;
+}
+
+}  // namespace siminf

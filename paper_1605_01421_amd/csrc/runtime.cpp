@@ -1,0 +1,788 @@
+// runtime.cpp -- host side of libsiminf.so: validation, layout of a run (or a
+// batch of runs) in device memory, event tables, launch configuration and the
+// C ABI declared in include/siminf.h.
+#include "siminf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "models.h"
+
+using namespace siminf;
+
+namespace {
+
+struct RunInfo {
+    int spec;
+    int group;
+    int64_t noff;  // global ordinal of the run's node 0
+    int32_t nn;
+    int64_t eoff;  // global ordinal of the run's event 0
+};
+
+struct Group {
+    int model = 0;
+    ModelShape shape{};
+    int n = 0;
+    int mode = 0;  // 0 free-running, 1 day-synchronous
+    int block = 256, blocks = 1;
+    KParams p{};
+    int64_t n_e1 = 0, n_e2 = 0, n_levels = 0;
+};
+
+template <class T>
+hipError_t to_device(std::vector<void*>& owned, const std::vector<T>& h, T** d) {
+    *d = nullptr;
+    size_t bytes = sizeof(T) * std::max<size_t>(h.size(), 1);
+    hipError_t e = hipMalloc((void**)d, bytes);
+    if (e != hipSuccess) return e;
+    owned.push_back((void*)*d);
+    if (!h.empty()) e = hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+template <class T>
+hipError_t alloc_device(std::vector<void*>& owned, size_t count, T** d) {
+    *d = nullptr;
+    hipError_t e = hipMalloc((void**)d, sizeof(T) * std::max<size_t>(count, 1));
+    if (e == hipSuccess) owned.push_back((void*)*d);
+    return e;
+}
+
+}  // namespace
+
+struct siminf_model {
+    int device = 0;
+    std::vector<void*> owned;
+    int nspec = 0, R = 0;
+    std::vector<RunInfo> runs;
+    int ntspan = 0, nb = 0, first_rec = 0;
+    double t0 = 0;
+    int64_t T1 = 0;
+    std::vector<int32_t> rec_off;
+    int record = 0, ncmax = 0, nvmax = 0;
+    int64_t total_nodes = 0, total_events = 0;
+    std::vector<Group> groups;
+    Ctrl* d_ctrl = nullptr;
+    unsigned long long *d_sums = nullptr, *d_sums_init = nullptr;
+    long long sums_len = 0;
+    int32_t* d_pos = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool pending = false, ran = false;
+    int status = 0;
+    int32_t err_code = 0, err_phase = -1, err_run = -1;
+    int64_t err_step = -1, err_index = -1;
+    uint64_t counters[3] = {0, 0, 0};
+    siminf_options opt{};
+};
+
+namespace {
+
+int hip_fail(siminf_model* m) {
+    if (m) m->status = SIMINF_E_DEVICE;
+    return SIMINF_E_DEVICE;
+}
+
+void set_create_error(siminf_model* m, int code, int64_t index, int run) {
+    m->err_code = code;
+    m->err_step = -1;
+    m->err_phase = -1;
+    m->err_index = index;
+    m->err_run = run;
+    m->status = code;
+}
+
+// Static validity check of one spec (section 3.4.2).  Returns 0 or a code;
+// *bad_event receives the offending event's input index (or -1).
+int validate_spec(const siminf_spec& s, int64_t* bad_event) {
+    *bad_event = -1;
+    ModelShape sh;
+    if (!model_shape(s.model, &sh)) return SIMINF_E_UNSUPPORTED;
+    if (s.Nc != sh.nc || s.Nt != sh.nt) return SIMINF_E_ARG;
+    if (s.Nv != sh.nv || s.Nld < sh.nld || s.Ngd < sh.ngd) return SIMINF_E_ARG;
+    if (s.Nn < 0 || s.Ntspan < 1 || s.Nev < 0 || s.Ecols < 0 || s.Ncols < 0) return SIMINF_E_ARG;
+    if (!s.S || !s.G || !s.tspan || (s.Nn > 0 && !s.u0)) return SIMINF_E_ARG;
+    if (sh.ngd > 0 && !s.gdata) return SIMINF_E_ARG;
+    if (s.Nn > 0 && s.Nv > 0 && !s.v0) return SIMINF_E_ARG;
+    if (s.Nn > 0 && s.Nld > 0 && !s.ldata) return SIMINF_E_ARG;
+    for (int k = 0; k < s.Ntspan; ++k)
+        if (!std::isfinite(s.tspan[k]) || (k > 0 && !(s.tspan[k] > s.tspan[k - 1]))) return SIMINF_E_ARG;
+    for (int64_t i = 0; i < (int64_t)s.Nn * s.Nc; ++i)
+        if (s.u0[i] < 0) return SIMINF_E_ARG;
+    if (s.Nev > 0) {
+        if (!s.ev_type || !s.ev_time || !s.ev_node || !s.ev_dest || !s.ev_n || !s.ev_select ||
+            !s.ev_shift || !s.ev_prop)
+            return SIMINF_E_ARG;
+        if (s.Ecols > 0 && !s.E) return SIMINF_E_ARG;
+        if (s.Ncols > 0 && !s.N) return SIMINF_E_ARG;
+    }
+    for (int e = 0; e < s.Nev; ++e) {
+        const int ty = s.ev_type[e];
+        bool ok = ty >= SIMINF_EXIT && ty <= SIMINF_EXTTRANS;
+        ok = ok && s.ev_node[e] >= 0 && s.ev_node[e] < s.Nn;
+        ok = ok && (ty != SIMINF_EXTTRANS || (s.ev_dest[e] >= 0 && s.ev_dest[e] < s.Nn));
+        ok = ok && s.ev_select[e] >= 0 && s.ev_select[e] < s.Ecols;
+        ok = ok && s.ev_n[e] >= 0;
+        ok = ok && s.ev_shift[e] >= -1 && s.ev_shift[e] < s.Ncols;
+        ok = ok && std::isfinite(s.ev_prop[e]) && s.ev_prop[e] >= 0.0 && s.ev_prop[e] <= 1.0;
+        if (ok) {
+            const int32_t* Ecol = s.E + (size_t)s.ev_select[e] * s.Nc;
+            bool any = false;
+            for (int c = 0; c < s.Nc; ++c) {
+                if (!Ecol[c]) continue;
+                any = true;
+                if (ty != SIMINF_ENTER && s.ev_shift[e] >= 0) {
+                    const int t = c + s.N[(size_t)s.ev_shift[e] * s.Nc + c];
+                    if (t < 0 || t >= s.Nc) ok = false;
+                }
+            }
+            if (ty == SIMINF_ENTER && !any) ok = false;
+        }
+        if (!ok) {
+            *bad_event = e;
+            return SIMINF_E_EVENT_INDEX;
+        }
+    }
+    return SIMINF_OK;
+}
+
+bool same_matrix(const int32_t* a, const int32_t* b, size_t n) {
+    return n == 0 || std::memcmp(a, b, sizeof(int32_t) * n) == 0;
+}
+
+int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const siminf_options* opt,
+                siminf_model** out) {
+    if (!out) return SIMINF_E_ARG;
+    *out = nullptr;
+    if (!specs || nspecs < 1) return SIMINF_E_ARG;
+    siminf_model* m = new (std::nothrow) siminf_model();
+    if (!m) return SIMINF_E_ALLOC;
+    *out = m;
+    if (opt) m->opt = *opt;
+    if (m->opt.record != SIMINF_RECORD_FULL && m->opt.record != SIMINF_RECORD_SUMS) {
+        set_create_error(m, SIMINF_E_ARG, -1, -1);
+        return SIMINF_E_ARG;
+    }
+    if (m->opt.block != 0 && (m->opt.block % 64 != 0 || m->opt.block < 64 || m->opt.block > 256)) {
+        set_create_error(m, SIMINF_E_ARG, -1, -1);
+        return SIMINF_E_ARG;
+    }
+    if (m->opt.lanes != 0 && m->opt.lanes != 1) {
+        set_create_error(m, SIMINF_E_UNSUPPORTED, -1, -1);
+        return SIMINF_E_UNSUPPORTED;
+    }
+    if (hipGetDevice(&m->device) != hipSuccess) return hip_fail(m);
+    m->record = m->opt.record;
+    m->nspec = nspecs;
+
+    // ---- validate every spec; shared tspan; one S/G/E/N per model ----------
+    for (int s = 0; s < nspecs; ++s) {
+        int64_t bad = -1;
+        const int rc = validate_spec(specs[s], &bad);
+        if (rc) {
+            set_create_error(m, rc, bad, -1);
+            return rc;
+        }
+        if (reps && reps[s] < 0) {
+            set_create_error(m, SIMINF_E_ARG, -1, -1);
+            return SIMINF_E_ARG;
+        }
+        if (specs[s].Ntspan != specs[0].Ntspan ||
+            std::memcmp(specs[s].tspan, specs[0].tspan, sizeof(double) * specs[0].Ntspan) != 0) {
+            set_create_error(m, SIMINF_E_ARG, -1, -1);
+            return SIMINF_E_ARG;
+        }
+    }
+    const siminf_spec& s0 = specs[0];
+    m->ntspan = s0.Ntspan;
+    m->t0 = s0.tspan[0];
+    const double tend = s0.tspan[s0.Ntspan - 1];
+    m->T1 = (int64_t)std::floor(m->t0) + 1;
+    m->nb = tend > m->t0 ? (int)(std::ceil(tend) - std::floor(m->t0)) : 0;
+    if ((uint32_t)m->nb >= MAX_STEPS) {
+        set_create_error(m, SIMINF_E_UNSUPPORTED, -1, -1);
+        return SIMINF_E_UNSUPPORTED;
+    }
+    m->rec_off.assign(m->nb + 1, 0);
+    {
+        int rec = 0;
+        while (rec < m->ntspan && s0.tspan[rec] <= m->t0) ++rec;
+        m->first_rec = rec;
+        m->rec_off[0] = rec;
+        for (int b = 0; b < m->nb; ++b) {
+            const double T = (double)(m->T1 + b);
+            while (rec < m->ntspan && s0.tspan[rec] <= T) ++rec;
+            m->rec_off[b + 1] = rec;
+        }
+    }
+
+    // ---- runs and model groups ---------------------------------------------
+    std::vector<int> group_of_model(8, -1);
+    std::vector<int> group_spec0;
+    int64_t noff = 0, eoff = 0;
+    for (int s = 0; s < nspecs; ++s) {
+        const int model = specs[s].model;
+        if (group_of_model[model] < 0) {
+            group_of_model[model] = (int)m->groups.size();
+            Group g;
+            g.model = model;
+            model_shape(model, &g.shape);
+            m->groups.push_back(g);
+            group_spec0.push_back(s);
+        } else {
+            const siminf_spec& a = specs[group_spec0[group_of_model[model]]];
+            const siminf_spec& b = specs[s];
+            bool same = a.Ecols == b.Ecols && a.Ncols == b.Ncols &&
+                        same_matrix(a.S, b.S, (size_t)a.Nc * a.Nt) && same_matrix(a.G, b.G, (size_t)a.Nt * a.Nt) &&
+                        same_matrix(a.E, b.E, (size_t)a.Nc * a.Ecols) && same_matrix(a.N, b.N, (size_t)a.Nc * a.Ncols);
+            if (!same) {
+                set_create_error(m, SIMINF_E_ARG, -1, -1);
+                return SIMINF_E_ARG;
+            }
+        }
+        const int nrep = reps ? reps[s] : 1;
+        for (int r = 0; r < nrep; ++r) {
+            RunInfo ri{s, group_of_model[model], noff, specs[s].Nn, eoff};
+            m->runs.push_back(ri);
+            noff += specs[s].Nn;
+            eoff += specs[s].Nev;
+        }
+        m->ncmax = std::max(m->ncmax, specs[s].Nc);
+        m->nvmax = std::max(m->nvmax, specs[s].Nv);
+    }
+    m->R = (int)m->runs.size();
+    m->total_nodes = noff;
+    m->total_events = eoff;
+    if ((uint64_t)noff >= MAX_ORDINAL || (uint64_t)eoff >= MAX_ORDINAL || m->R >= (1 << 24) ||
+        m->groups.size() > (size_t)MAX_GROUPS) {
+        set_create_error(m, SIMINF_E_UNSUPPORTED, -1, -1);
+        return SIMINF_E_UNSUPPORTED;
+    }
+    bool any_e2 = false;
+    for (int s = 0; s < nspecs; ++s)
+        for (int e = 0; e < specs[s].Nev; ++e) any_e2 |= specs[s].ev_type[e] == SIMINF_EXTTRANS;
+    if (any_e2 && m->groups.size() > 1) {
+        set_create_error(m, SIMINF_E_ARG, -1, -1);
+        return SIMINF_E_ARG;
+    }
+
+    // ---- shared device tables ------------------------------------------------
+    int ngd_max = 0;
+    for (int s = 0; s < nspecs; ++s) ngd_max = std::max(ngd_max, specs[s].Ngd);
+    std::vector<double> gdata((size_t)nspecs * std::max(ngd_max, 1), 0.0);
+    for (int s = 0; s < nspecs; ++s)
+        for (int k = 0; k < specs[s].Ngd; ++k) gdata[(size_t)s * ngd_max + k] = specs[s].gdata[k];
+    std::vector<int32_t> run_spec(m->R);
+    for (int r = 0; r < m->R; ++r) run_spec[r] = m->runs[r].spec;
+    double* d_gdata;
+    int32_t *d_run_spec, *d_rec_off;
+    if (to_device(m->owned, gdata, &d_gdata) || to_device(m->owned, run_spec, &d_run_spec) ||
+        to_device(m->owned, m->rec_off, &d_rec_off))
+        return hip_fail(m);
+    if (alloc_device(m->owned, 1, &m->d_ctrl) || hipMemset(m->d_ctrl, 0, sizeof(Ctrl)) != hipSuccess)
+        return hip_fail(m);
+    std::vector<int32_t> pos(std::max<int64_t>(m->total_nodes, 1), 0);
+
+    if (m->record == SIMINF_RECORD_SUMS) {
+        m->sums_len = (long long)m->R * m->ntspan * m->ncmax;
+        std::vector<unsigned long long> init(m->sums_len, 0ull);
+        for (int r = 0; r < m->R; ++r) {
+            const siminf_spec& s = specs[m->runs[r].spec];
+            for (int mm = 0; mm < m->first_rec; ++mm)
+                for (int i = 0; i < s.Nn; ++i)
+                    for (int c = 0; c < s.Nc; ++c)
+                        init[((size_t)r * m->ntspan + mm) * m->ncmax + c] += (unsigned long long)s.u0[(size_t)i * s.Nc + c];
+        }
+        if (to_device(m->owned, init, &m->d_sums_init) || alloc_device(m->owned, m->sums_len, &m->d_sums))
+            return hip_fail(m);
+    }
+
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess)
+        return hip_fail(m);
+
+    // ---- per model group -------------------------------------------------------
+    for (size_t gi = 0; gi < m->groups.size(); ++gi) {
+        Group& g = m->groups[gi];
+        const siminf_spec& sp = specs[group_spec0[gi]];
+        const int nc = g.shape.nc, nv = g.shape.nv, nld = g.shape.nld;
+        // nodes of this group, in input order, then binned
+        struct NodeRef {
+            int run;
+            int32_t idx;
+            int64_t work;
+        };
+        std::vector<NodeRef> nodes;
+        std::vector<int> grp_runs;
+        for (int r = 0; r < m->R; ++r)
+            if (m->runs[r].group == (int)gi) grp_runs.push_back(r);
+        for (int r : grp_runs) {
+            const siminf_spec& s = specs[m->runs[r].spec];
+            std::vector<int64_t> nev(s.Nn, 0);
+            for (int e = 0; e < s.Nev; ++e) nev[s.ev_node[e]] += 1;
+            for (int i = 0; i < s.Nn; ++i) {
+                int64_t w = 0;
+                for (int c = 0; c < s.Nc; ++c) w += s.u0[(size_t)i * s.Nc + c];
+                nodes.push_back({r, i, w + 8 * nev[i]});
+            }
+        }
+        if (m->opt.order == 0)
+            std::stable_sort(nodes.begin(), nodes.end(),
+                             [](const NodeRef& a, const NodeRef& b) { return a.work > b.work; });
+        const int n = (int)nodes.size();
+        g.n = n;
+        std::vector<int32_t> u0s((size_t)nc * n), node_run(n), node_idx(n);
+        std::vector<double> v0s((size_t)nv * n), lds((size_t)nld * n);
+        std::vector<int64_t> node_ord(n);
+        for (int k = 0; k < n; ++k) {
+            const NodeRef& nr = nodes[k];
+            const siminf_spec& s = specs[m->runs[nr.run].spec];
+            for (int c = 0; c < nc; ++c) u0s[(size_t)c * n + k] = s.u0[(size_t)nr.idx * nc + c];
+            for (int c = 0; c < nv; ++c) v0s[(size_t)c * n + k] = s.v0[(size_t)nr.idx * nv + c];
+            for (int l = 0; l < nld; ++l) lds[(size_t)l * n + k] = s.ldata[(size_t)nr.idx * s.Nld + l];
+            node_run[k] = nr.run;
+            node_idx[k] = nr.idx;
+            node_ord[k] = m->runs[nr.run].noff + nr.idx;
+            pos[m->runs[nr.run].noff + nr.idx] = k;
+        }
+        // events: E1 in node-major CSR, E2 grouped by step and conflict level
+        struct Ev {
+            int run;
+            int32_t e;
+        };
+        std::vector<Ev> e1, e2;
+        for (int r : grp_runs) {
+            const siminf_spec& s = specs[m->runs[r].spec];
+            for (int e = 0; e < s.Nev; ++e)
+                (s.ev_type[e] == SIMINF_EXTTRANS ? e2 : e1).push_back({r, e});
+        }
+        auto local = [&](int run, int32_t i) { return pos[m->runs[run].noff + i]; };
+        auto S_of = [&](int run) -> const siminf_spec& { return specs[m->runs[run].spec]; };
+        std::stable_sort(e1.begin(), e1.end(), [&](const Ev& a, const Ev& b) {
+            const siminf_spec &sa = S_of(a.run), &sb = S_of(b.run);
+            const int ka = local(a.run, sa.ev_node[a.e]), kb = local(b.run, sb.ev_node[b.e]);
+            return std::make_tuple(ka, sa.ev_time[a.e], sa.ev_type[a.e], a.e) <
+                   std::make_tuple(kb, sb.ev_time[b.e], sb.ev_type[b.e], b.e);
+        });
+        std::vector<int32_t> e1_off(n + 1, 0);
+        for (const Ev& x : e1) e1_off[local(x.run, S_of(x.run).ev_node[x.e]) + 1] += 1;
+        for (int k = 0; k < n; ++k) e1_off[k + 1] += e1_off[k];
+        // step of an external transfer: first boundary T >= its time
+        auto step_of = [&](const Ev& x) -> int64_t {
+            const int64_t t = S_of(x.run).ev_time[x.e];
+            return std::max<int64_t>(0, t - m->T1);
+        };
+        std::vector<Ev> e2k;
+        for (const Ev& x : e2)
+            if (step_of(x) < m->nb) e2k.push_back(x);
+        std::stable_sort(e2k.begin(), e2k.end(), [&](const Ev& a, const Ev& b) {
+            return std::make_tuple(step_of(a), S_of(a.run).ev_time[a.e], a.run, a.e) <
+                   std::make_tuple(step_of(b), S_of(b.run).ev_time[b.e], b.run, b.e);
+        });
+        // conflict levels: an event's level is one more than the latest level of
+        // any earlier same-step event touching its source or destination node
+        std::vector<int32_t> lvl(e2k.size(), 0), last(n, -1);
+        std::vector<int32_t> touched;
+        std::vector<int32_t> e2_step(m->nb + 1, 0);
+        std::vector<int32_t> e2_lvl;
+        std::vector<size_t> order2;
+        {
+            size_t a = 0;
+            int32_t level_base = 0;
+            for (int b = 0; b < m->nb; ++b) {
+                e2_step[b] = level_base;
+                size_t z = a;
+                int depth = 0;
+                while (z < e2k.size() && step_of(e2k[z]) == b) {
+                    const siminf_spec& s = S_of(e2k[z].run);
+                    const int src = local(e2k[z].run, s.ev_node[e2k[z].e]);
+                    const int dst = local(e2k[z].run, s.ev_dest[e2k[z].e]);
+                    const int L = std::max(last[src], last[dst]) + 1;
+                    lvl[z] = L;
+                    last[src] = last[dst] = L;
+                    touched.push_back(src);
+                    touched.push_back(dst);
+                    depth = std::max(depth, L + 1);
+                    ++z;
+                }
+                std::vector<size_t> idx(z - a);
+                std::iota(idx.begin(), idx.end(), a);
+                std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return lvl[x] < lvl[y]; });
+                size_t c = 0;
+                for (int L = 0; L < depth; ++L) {
+                    e2_lvl.push_back((int32_t)order2.size());
+                    while (c < idx.size() && lvl[idx[c]] == L) order2.push_back(idx[c++]);
+                }
+                level_base += depth;
+                for (int t : touched) last[t] = -1;
+                touched.clear();
+                a = z;
+            }
+            e2_step[m->nb] = level_base;
+            e2_lvl.push_back((int32_t)order2.size());
+        }
+        g.n_e1 = (int64_t)e1.size();
+        g.n_e2 = (int64_t)order2.size();
+        g.n_levels = (int64_t)e2_lvl.size() - 1;
+        g.mode = g.n_e2 > 0 ? 1 : 0;
+
+        auto fill = [&](const std::vector<Ev>& list, const std::vector<size_t>* perm, EventSoA* soa,
+                        bool with_dest) -> bool {
+            const size_t cnt = perm ? perm->size() : list.size();
+            std::vector<int32_t> time(cnt), type(cnt), nn(cnt), sel(cnt), sh(cnt), id(cnt), nd(cnt), ds(cnt);
+            std::vector<double> prop(cnt);
+            std::vector<int64_t> ord(cnt);
+            for (size_t j = 0; j < cnt; ++j) {
+                const Ev& x = perm ? list[(*perm)[j]] : list[j];
+                const siminf_spec& s = S_of(x.run);
+                time[j] = s.ev_time[x.e];
+                type[j] = s.ev_type[x.e];
+                nn[j] = s.ev_n[x.e];
+                sel[j] = s.ev_select[x.e];
+                sh[j] = s.ev_shift[x.e];
+                id[j] = x.e;
+                prop[j] = s.ev_prop[x.e];
+                ord[j] = m->runs[x.run].eoff + x.e;
+                nd[j] = local(x.run, s.ev_node[x.e]);
+                ds[j] = with_dest ? local(x.run, s.ev_dest[x.e]) : 0;
+            }
+            int32_t *a1, *a2, *a3, *a4, *a5, *a6, *a7, *a8;
+            double* a9;
+            int64_t* a10;
+            if (to_device(m->owned, time, &a1) || to_device(m->owned, type, &a2) || to_device(m->owned, nn, &a3) ||
+                to_device(m->owned, sel, &a4) || to_device(m->owned, sh, &a5) || to_device(m->owned, id, &a6) ||
+                to_device(m->owned, nd, &a7) || to_device(m->owned, ds, &a8) || to_device(m->owned, prop, &a9) ||
+                to_device(m->owned, ord, &a10))
+                return false;
+            *soa = EventSoA{a1, a2, a3, a4, a5, a6, a10, a9, a7, a8};
+            return true;
+        };
+        KParams& p = g.p;
+        p = KParams{};
+        p.n = n;
+        p.nb = m->nb;
+        p.ntspan = m->ntspan;
+        p.mode = g.mode;
+        p.T1 = m->T1;
+        p.t0 = m->t0;
+        p.ngd = std::max(ngd_max, 1);
+        for (int j = 0; j < g.shape.nt; ++j) {
+            for (int c = 0; c < nc; ++c) p.S[c + j * nc] = sp.S[c + (size_t)j * nc];
+            uint32_t mask = 0;
+            for (int k = 0; k < g.shape.nt; ++k)
+                if (sp.G[k + (size_t)j * g.shape.nt]) mask |= 1u << k;
+            p.Gmask[j] = mask;
+        }
+        std::vector<uint32_t> emask(std::max(sp.Ecols, 1), 0u);
+        for (int s = 0; s < sp.Ecols; ++s)
+            for (int c = 0; c < nc; ++c)
+                if (sp.E[(size_t)s * nc + c]) emask[s] |= 1u << c;
+        std::vector<int32_t> nshift((size_t)std::max(sp.Ncols, 1) * MAX_NC, 0);
+        for (int q = 0; q < sp.Ncols; ++q)
+            for (int c = 0; c < nc; ++c) nshift[(size_t)q * MAX_NC + c] = sp.N[(size_t)q * nc + c];
+        p.ecols = sp.Ecols;
+        p.ncols = sp.Ncols;
+        uint32_t* d_emask;
+        int32_t *d_nshift, *d_u0, *d_nrun, *d_nidx, *d_e1off, *d_e2step, *d_e2lvl;
+        double *d_v0, *d_ld;
+        int64_t* d_nord;
+        if (to_device(m->owned, emask, &d_emask) || to_device(m->owned, nshift, &d_nshift) ||
+            to_device(m->owned, u0s, &d_u0) || to_device(m->owned, v0s, &d_v0) || to_device(m->owned, lds, &d_ld) ||
+            to_device(m->owned, node_run, &d_nrun) || to_device(m->owned, node_idx, &d_nidx) ||
+            to_device(m->owned, node_ord, &d_nord) || to_device(m->owned, e1_off, &d_e1off) ||
+            to_device(m->owned, e2_step, &d_e2step) || to_device(m->owned, e2_lvl, &d_e2lvl))
+            return hip_fail(m);
+        if (!fill(e1, nullptr, &p.e1, false) || !fill(e2k, &order2, &p.e2, true)) return hip_fail(m);
+        p.Emask = d_emask;
+        p.Nshift = d_nshift;
+        p.rec_off = d_rec_off;
+        p.u0 = d_u0;
+        p.v0 = d_v0;
+        p.ld = d_ld;
+        p.node_run = d_nrun;
+        p.node_idx = d_nidx;
+        p.node_ord = d_nord;
+        p.gdata = d_gdata;
+        p.run_spec = d_run_spec;
+        p.e1_off = d_e1off;
+        p.e2_step = d_e2step;
+        p.e2_lvl = d_e2lvl;
+        if (g.mode == 1) {
+            if (alloc_device(m->owned, (size_t)nc * n, &p.u) || alloc_device(m->owned, (size_t)std::max(nv, 1) * n, &p.v) ||
+                alloc_device(m->owned, (size_t)n, &p.e1_cur))
+                return hip_fail(m);
+        }
+        p.record = m->record;
+        p.sums_nc = m->ncmax;
+        p.sums = m->d_sums;
+        if (m->record == SIMINF_RECORD_FULL) {
+            if (alloc_device(m->owned, (size_t)m->ntspan * nc * n, &p.U) ||
+                alloc_device(m->owned, (size_t)m->ntspan * std::max(nv, 1) * n, &p.V))
+                return hip_fail(m);
+        }
+        p.ctrl = m->d_ctrl;
+        p.group = (int)gi;
+        p.nchunks = (n + WAVE - 1) / WAVE;
+
+        // launch shape
+        int block = m->opt.block;
+        if (block == 0) block = g.mode == 1 ? 64 : 256;
+        const int per_cu = max_blocks_per_cu(g.model, g.mode, block);
+        if (per_cu <= 0) return hip_fail(m);
+        const int cap = per_cu * cus;
+        int blocks;
+        if (g.mode == 1)
+            blocks = std::max(1, std::min(cap, (n + block - 1) / block));
+        else
+            blocks = std::max(1, std::min(cap, (p.nchunks + block / WAVE - 1) / (block / WAVE)));
+        if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
+        g.block = block;
+        g.blocks = blocks;
+        p.nblocks = blocks;
+    }
+    if (to_device(m->owned, pos, &m->d_pos)) return hip_fail(m);
+    return SIMINF_OK;
+}
+
+void decode_error(siminf_model* m, uint64_t key) {
+    m->err_code = -(int32_t)(key & 0xF);
+    m->err_step = (int64_t)(key >> 44);
+    m->err_phase = (int32_t)((key >> 42) & 3);
+    const int64_t ord = (int64_t)((key >> 4) & ((1ull << 38) - 1));
+    const bool node_phase = m->err_phase == PH_SSA || m->err_phase == PH_PTS;
+    int lo = 0, hi = m->R - 1, run = 0;
+    while (lo <= hi) {
+        const int mid = (lo + hi) / 2;
+        const int64_t off = node_phase ? m->runs[mid].noff : m->runs[mid].eoff;
+        if (off <= ord) {
+            run = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    // skip empty runs that share the same offset
+    if (node_phase)
+        while (run + 1 < m->R && m->runs[run + 1].noff <= ord && m->runs[run].nn == 0) ++run;
+    m->err_run = run;
+    m->err_index = ord - (node_phase ? m->runs[run].noff : m->runs[run].eoff);
+}
+
+int finish(siminf_model* m) {
+    if (!m->pending) return m->status;
+    m->pending = false;
+    if (hipStreamSynchronize(m->last_stream) != hipSuccess) return hip_fail(m);
+    Ctrl c;
+    if (hipMemcpy(&c, m->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail(m);
+    for (int i = 0; i < 3; ++i) m->counters[i] = c.counters[i];
+    m->err_code = 0;
+    m->err_step = -1;
+    m->err_phase = -1;
+    m->err_index = -1;
+    m->err_run = -1;
+    if (c.abort) {
+        m->err_code = SIMINF_E_DEVICE;
+        m->status = SIMINF_E_DEVICE;
+        return m->status;
+    }
+    if (c.err_key != NO_ERROR) decode_error(m, c.err_key);
+    m->status = m->err_code;
+    return m->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int siminf_create(const siminf_spec* spec, const siminf_options* opt, siminf_model** out) {
+    return create_impl(spec, 1, nullptr, opt, out);
+}
+
+int siminf_create_batch(const siminf_spec* specs, int32_t nspecs, const int32_t* replicates,
+                        const siminf_options* opt, siminf_model** out) {
+    return create_impl(specs, nspecs, replicates, opt, out);
+}
+
+int siminf_run(siminf_model* m, uint64_t seed, uint32_t stream_base, void* hip_stream) {
+    if (!m) return SIMINF_E_ARG;
+    if ((uint64_t)stream_base + (uint64_t)m->R > (1ull << 24)) return SIMINF_E_ARG;
+    if (m->pending) finish(m);
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (size_t gi = 0; gi < m->groups.size(); ++gi) {
+        Group& g = m->groups[gi];
+        g.p.seed = seed;
+        g.p.stream_base = stream_base;
+        if (launch_init(g.p, g.shape.nc, g.shape.nv, m->first_rec, gi == 0,
+                        gi == 0 ? m->d_sums_init : nullptr, gi == 0 ? m->sums_len : 0, st) != hipSuccess)
+            return hip_fail(m);
+    }
+    if (m->groups.empty()) {
+        KParams p{};
+        p.ctrl = m->d_ctrl;
+        p.sums = m->d_sums;
+        if (launch_init(p, 0, 0, 0, true, m->d_sums_init, m->sums_len, st) != hipSuccess) return hip_fail(m);
+    }
+    for (Group& g : m->groups) {
+        if (g.n == 0) continue;
+        if (launch_group(g.model, g.p, g.block, g.blocks, g.mode == 1, st) != hipSuccess) return hip_fail(m);
+    }
+    m->last_stream = st;
+    m->pending = true;
+    m->ran = true;
+    m->status = 0;
+    return SIMINF_OK;
+}
+
+int siminf_wait(siminf_model* m) {
+    if (!m) return SIMINF_E_ARG;
+    return finish(m);
+}
+
+int siminf_trajectory(siminf_model* m, int32_t run, int32_t* U, double* V, int32_t dst_is_device) {
+    if (!m || run < 0 || run >= m->R) return SIMINF_E_ARG;
+    if (m->record != SIMINF_RECORD_FULL) return SIMINF_E_ARG;
+    if (!m->ran) return SIMINF_E_ARG;
+    finish(m);
+    const RunInfo& ri = m->runs[run];
+    const Group& g = m->groups[ri.group];
+    const int nc = g.shape.nc, nv = g.shape.nv;
+    const size_t nU = (size_t)m->ntspan * ri.nn * nc, nV = (size_t)m->ntspan * ri.nn * nv;
+    if (ri.nn == 0) return SIMINF_OK;
+    int32_t* dU = nullptr;
+    double* dV = nullptr;
+    bool tmpU = false, tmpV = false;
+    if (U) {
+        if (dst_is_device) dU = U;
+        else if (hipMalloc((void**)&dU, sizeof(int32_t) * nU) != hipSuccess) return SIMINF_E_ALLOC;
+        else tmpU = true;
+    }
+    if (V && nv > 0) {
+        if (dst_is_device) dV = V;
+        else if (hipMalloc((void**)&dV, sizeof(double) * nV) != hipSuccess) {
+            if (tmpU) (void)hipFree(dU);
+            return SIMINF_E_ALLOC;
+        } else tmpV = true;
+    }
+    int rc = SIMINF_OK;
+    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, m->d_pos + ri.noff, ri.nn, dU, dV, nullptr) !=
+            hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        rc = SIMINF_E_DEVICE;
+    if (rc == SIMINF_OK && tmpU && hipMemcpy(U, dU, sizeof(int32_t) * nU, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = SIMINF_E_DEVICE;
+    if (rc == SIMINF_OK && tmpV && hipMemcpy(V, dV, sizeof(double) * nV, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = SIMINF_E_DEVICE;
+    if (tmpU) (void)hipFree(dU);
+    if (tmpV) (void)hipFree(dV);
+    return rc;
+}
+
+int siminf_sums(siminf_model* m, int64_t* sums, int32_t dst_is_device) {
+    if (!m || !sums || m->record != SIMINF_RECORD_SUMS || !m->ran) return SIMINF_E_ARG;
+    finish(m);
+    const size_t bytes = sizeof(int64_t) * (size_t)m->sums_len;
+    if (bytes == 0) return SIMINF_OK;
+    if (hipMemcpy(sums, m->d_sums, bytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return SIMINF_E_DEVICE;
+    return SIMINF_OK;
+}
+
+int siminf_counters(siminf_model* m, uint64_t out[3]) {
+    if (!m || !out) return SIMINF_E_ARG;
+    finish(m);
+    for (int i = 0; i < 3; ++i) out[i] = m->counters[i];
+    return SIMINF_OK;
+}
+
+int siminf_shape(const siminf_model* m, int64_t out[6]) {
+    if (!m || !out) return SIMINF_E_ARG;
+    out[0] = m->R;
+    out[1] = m->total_nodes;
+    out[2] = m->ntspan;
+    out[3] = m->ncmax;
+    out[4] = m->nvmax;
+    out[5] = m->nb;
+    return SIMINF_OK;
+}
+
+int siminf_error_info(const siminf_model* m, int32_t* code, int64_t* step, int32_t* phase, int64_t* index,
+                      int32_t* run) {
+    if (!m) return SIMINF_E_ARG;
+    if (code) *code = m->err_code;
+    if (step) *step = m->err_step;
+    if (phase) *phase = m->err_phase;
+    if (index) *index = m->err_index;
+    if (run) *run = m->err_run;
+    return SIMINF_OK;
+}
+
+int siminf_launch_info(const siminf_model* m, int32_t out[5]) {
+    if (!m || !out) return SIMINF_E_ARG;
+    if (m->groups.empty()) {
+        for (int i = 0; i < 5; ++i) out[i] = 0;
+        return SIMINF_OK;
+    }
+    const Group& g = m->groups[0];
+    out[0] = g.block;
+    out[1] = g.blocks;
+    out[2] = g.mode;
+    out[3] = 1;
+    out[4] = m->opt.order;
+    return SIMINF_OK;
+}
+
+void siminf_destroy(siminf_model* m) {
+    if (!m) return;
+    if (m->pending) finish(m);
+    for (void* p : m->owned) (void)hipFree(p);
+    delete m;
+}
+
+const char* siminf_status_string(int32_t code) {
+    switch (code) {
+        case SIMINF_OK: return "SIMINF_OK";
+        case SIMINF_E_ARG: return "SIMINF_E_ARG";
+        case SIMINF_E_UNSUPPORTED: return "SIMINF_E_UNSUPPORTED";
+        case SIMINF_E_ALLOC: return "SIMINF_E_ALLOC";
+        case SIMINF_E_DEVICE: return "SIMINF_E_DEVICE";
+        case SIMINF_E_NEG_STATE: return "SIMINF_E_NEG_STATE";
+        case SIMINF_E_BAD_RATE: return "SIMINF_E_BAD_RATE";
+        case SIMINF_E_EVENT_OVERDRAW: return "SIMINF_E_EVENT_OVERDRAW";
+        case SIMINF_E_EVENT_INDEX: return "SIMINF_E_EVENT_INDEX";
+        case SIMINF_E_PTS: return "SIMINF_E_PTS";
+    }
+    return "SIMINF_UNKNOWN";
+}
+
+int siminf_prevalence_quantiles(siminf_model* m, int32_t case_c, uint32_t at_risk_mask, int32_t replicates,
+                                int32_t k0, int32_t nk, const double* probs, int32_t nq, float* out,
+                                void* hip_stream) {
+    if (!m || !probs || !out || m->record != SIMINF_RECORD_SUMS || !m->ran) return SIMINF_E_ARG;
+    if (replicates < 1 || m->R % replicates != 0 || case_c < 0 || case_c >= m->ncmax || nq < 1 || nk < 0 ||
+        k0 < 0 || k0 + nk > m->ntspan || replicates > 4096)
+        return SIMINF_E_ARG;
+    for (int q = 0; q < nq; ++q)
+        if (!(probs[q] >= 0.0 && probs[q] <= 1.0)) return SIMINF_E_ARG;
+    double* d_probs = nullptr;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (hipMalloc((void**)&d_probs, sizeof(double) * nq) != hipSuccess) return SIMINF_E_ALLOC;
+    int rc = SIMINF_OK;
+    if (hipMemcpy(d_probs, probs, sizeof(double) * nq, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_prevalence(m->d_sums, m->R, m->ntspan, m->ncmax, case_c, at_risk_mask, replicates, k0, nk, d_probs,
+                          nq, out, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = SIMINF_E_DEVICE;
+    (void)hipFree(d_probs);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+"""ctypes binding of libsiminf.so (the C ABI in include/siminf.h).
+
+Argument marshalling only: every step of a run executes in the library's HIP
+kernels.  PyTorch is used for device memory and streams where the caller
+wants device-resident results.  Loading fails loudly when the library is
+missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsiminf.so")
+
+SIMINF_OK = 0
+STATUS = {0: "SIMINF_OK", -1: "SIMINF_E_ARG", -2: "SIMINF_E_UNSUPPORTED", -3: "SIMINF_E_ALLOC",
+          -4: "SIMINF_E_DEVICE", -5: "SIMINF_E_NEG_STATE", -6: "SIMINF_E_BAD_RATE",
+          -7: "SIMINF_E_EVENT_OVERDRAW", -8: "SIMINF_E_EVENT_INDEX", -9: "SIMINF_E_PTS"}
+RECORD_FULL, RECORD_SUMS = 0, 1
+
+
+class SiminfError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+
+
+class Spec(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("model", "Nc", "Nt", "Nn", "Nv", "Nld", "Ngd", "Ntspan")] + [
+        ("S", ctypes.c_void_p), ("G", ctypes.c_void_p), ("u0", ctypes.c_void_p),
+        ("v0", ctypes.c_void_p), ("ldata", ctypes.c_void_p), ("gdata", ctypes.c_void_p),
+        ("tspan", ctypes.c_void_p),
+        ("Nev", ctypes.c_int32), ("Ecols", ctypes.c_int32), ("Ncols", ctypes.c_int32),
+        ("ev_type", ctypes.c_void_p), ("ev_time", ctypes.c_void_p), ("ev_node", ctypes.c_void_p),
+        ("ev_dest", ctypes.c_void_p), ("ev_n", ctypes.c_void_p), ("ev_select", ctypes.c_void_p),
+        ("ev_shift", ctypes.c_void_p), ("ev_prop", ctypes.c_void_p),
+        ("E", ctypes.c_void_p), ("N", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("record", ctypes.c_int32), ("block", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+# exported entry points: name -> (restype, argtypes)
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "siminf_create": (ctypes.c_int, [ctypes.POINTER(Spec), ctypes.POINTER(Options), ctypes.POINTER(_P)]),
+    "siminf_create_batch": (ctypes.c_int, [ctypes.POINTER(Spec), ctypes.c_int32, _P,
+                                           ctypes.POINTER(Options), ctypes.POINTER(_P)]),
+    "siminf_run": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint32, _P]),
+    "siminf_wait": (ctypes.c_int, [_P]),
+    "siminf_trajectory": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "siminf_sums": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "siminf_counters": (ctypes.c_int, [_P, _P]),
+    "siminf_shape": (ctypes.c_int, [_P, _P]),
+    "siminf_error_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "siminf_launch_info": (ctypes.c_int, [_P, _P]),
+    "siminf_destroy": (None, [_P]),
+    "siminf_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "siminf_prevalence_quantiles": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
+                                                   ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                                   _P, _P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsiminf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1605_01421_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
+
+
+def _marshal(spec, keep: list) -> Spec:
+    """Fill a siminf_spec from a model specification object (see workloads)."""
+    S = np.asarray(spec.S)
+    Nc, Nt = S.shape
+    u0 = _c(spec.u0, np.int32)
+    Nn = u0.shape[0]
+    v0 = _c(np.asarray(spec.v0, dtype=np.float64).reshape(Nn, -1), np.float64)
+    ld = _c(np.asarray(spec.ldata, dtype=np.float64).reshape(Nn, -1), np.float64)
+    E = np.asarray(spec.E)
+    N = np.asarray(spec.N)
+    arrays = dict(S=_c(S.ravel(order="F"), np.int32), G=_c(np.asarray(spec.G).ravel(order="F"), np.int32),
+                  u0=u0, v0=v0, ldata=ld, gdata=_c(spec.gdata, np.float64),
+                  tspan=_c(spec.tspan, np.float64), E=_c(E.ravel(order="F"), np.int32),
+                  N=_c(N.ravel(order="F"), np.int32))
+    ev = spec.events
+    for k in ("event", "time", "node", "dest", "n", "select", "shift"):
+        arrays["ev_" + k] = _c(ev[k], np.int32)
+    arrays["ev_prop"] = _c(ev["proportion"], np.float64)
+    keep.append(arrays)
+    s = Spec()
+    s.model = int(spec.model)
+    s.Nc, s.Nt, s.Nn = Nc, Nt, Nn
+    s.Nv, s.Nld = v0.shape[1], ld.shape[1]
+    s.Ngd, s.Ntspan = arrays["gdata"].size, arrays["tspan"].size
+    for f in ("S", "G", "u0", "v0", "ldata", "gdata", "tspan", "E", "N"):
+        setattr(s, f, _ptr(arrays[f]))
+    s.Nev = arrays["ev_event"].size
+    s.Ecols = E.shape[1] if E.ndim == 2 else 0
+    s.Ncols = N.shape[1] if N.ndim == 2 else 0
+    s.ev_type = _ptr(arrays["ev_event"])
+    for k in ("time", "node", "dest", "n", "select", "shift", "prop"):
+        setattr(s, "ev_" + k, _ptr(arrays["ev_" + k]))
+    return s
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Model:
+    """A run (or a batch of runs) resident on the current HIP device.
+
+    ``Model(spec)`` creates one run; ``Model([(spec, replicates), ...])`` a
+    batch.  ``run`` enqueues the whole simulation on a HIP stream (torch's
+    current stream by default); ``wait``/``trajectory``/``sums``/``counters``
+    synchronise."""
+
+    def __init__(self, spec, record: int = RECORD_FULL, block: int = 0, order: int = 0,
+                 lanes: int = 1, max_blocks: int = 0):
+        lib = load()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        opt = Options(record, block, order, lanes, max_blocks)
+        keep: list = []
+        if isinstance(spec, (list, tuple)):
+            specs = [s for s, _ in spec]
+            reps = np.asarray([r for _, r in spec], dtype=np.int32)
+            arr = (Spec * len(specs))(*[_marshal(s, keep) for s in specs])
+            rc = lib.siminf_create_batch(arr, len(specs), _ptr(reps), ctypes.byref(opt), ctypes.byref(self._h))
+            self.specs = specs
+            self.replicates = [int(r) for r in reps]
+        else:
+            s = _marshal(spec, keep)
+            rc = lib.siminf_create(ctypes.byref(s), ctypes.byref(opt), ctypes.byref(self._h))
+            self.specs = [spec]
+            self.replicates = [1]
+        self.record = record
+        if rc != SIMINF_OK:
+            info = self.error_info() if self._h.value else None
+            self.close()
+            err = SiminfError(rc, "siminf_create")
+            err.info = info
+            raise err
+        shape = np.zeros(6, dtype=np.int64)
+        lib.siminf_shape(self._h, _ptr(shape))
+        self.runs, self.total_nodes, self.ntspan, self.ncmax, self.nvmax, self.n_steps = (int(x) for x in shape)
+        self.run_spec = [k for k, r in enumerate(self.replicates) for _ in range(r)]
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.siminf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- running -------------------------------------------------------------
+    def run(self, seed: int, stream_base: int = 0, hip_stream=None):
+        rc = self._lib.siminf_run(self._h, ctypes.c_uint64(seed & (2**64 - 1)),
+                                  ctypes.c_uint32(stream_base), _stream_handle(hip_stream))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_run")
+        return self
+
+    def wait(self) -> int:
+        return int(self._lib.siminf_wait(self._h))
+
+    def error_info(self) -> dict:
+        code = ctypes.c_int32()
+        step = ctypes.c_int64()
+        phase = ctypes.c_int32()
+        index = ctypes.c_int64()
+        run = ctypes.c_int32()
+        self._lib.siminf_error_info(self._h, ctypes.byref(code), ctypes.byref(step), ctypes.byref(phase),
+                                    ctypes.byref(index), ctypes.byref(run))
+        return dict(code=code.value, name=STATUS.get(code.value, str(code.value)), step=step.value,
+                    phase=phase.value, index=index.value, run=run.value)
+
+    def counters(self) -> dict:
+        out = np.zeros(3, dtype=np.uint64)
+        rc = self._lib.siminf_counters(self._h, _ptr(out))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_counters")
+        return dict(transitions=int(out[0]), node_days=int(out[1]), events=int(out[2]))
+
+    def launch_info(self) -> dict:
+        out = np.zeros(5, dtype=np.int32)
+        self._lib.siminf_launch_info(self._h, _ptr(out))
+        return dict(block=int(out[0]), blocks=int(out[1]), mode=int(out[2]), lanes=int(out[3]),
+                    order=int(out[4]))
+
+    # -- results ---------------------------------------------------------------
+    def trajectory(self, run: int = 0, device: bool = False):
+        """U (Ntspan, Nn, Nc) int32 and V (Ntspan, Nn, Nv) float64 of one run --
+        the paper's column-major U/V viewed per time point.  With
+        device=True they are torch tensors on the current device."""
+        spec = self.specs[self.run_spec[run]]
+        Nn, Nc = spec.u0.shape
+        Nv = np.asarray(spec.v0).reshape(Nn, -1).shape[1] if Nn else 0
+        if device:
+            import torch
+            U = torch.empty((self.ntspan, Nn, Nc), dtype=torch.int32, device="cuda")
+            V = torch.empty((self.ntspan, Nn, Nv), dtype=torch.float64, device="cuda")
+            rc = self._lib.siminf_trajectory(self._h, run, ctypes.c_void_p(U.data_ptr()),
+                                             ctypes.c_void_p(V.data_ptr()) if Nv else None, 1)
+        else:
+            U = np.empty((self.ntspan, Nn, Nc), dtype=np.int32)
+            V = np.empty((self.ntspan, Nn, Nv), dtype=np.float64)
+            rc = self._lib.siminf_trajectory(self._h, run, _ptr(U), _ptr(V), 0)
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_trajectory")
+        return U, V
+
+    def sums(self) -> np.ndarray:
+        """Per-run compartment sums over nodes, int64 (runs, Ntspan, Nc_max)."""
+        out = np.empty((self.runs, self.ntspan, self.ncmax), dtype=np.int64)
+        rc = self._lib.siminf_sums(self._h, _ptr(out), 0)
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_sums")
+        return out
+
+    def prevalence_quantiles(self, case_c: int, at_risk, replicates: int, k0: int, nk: int,
+                             probs=(0.1, 0.5, 0.9), hip_stream=None):
+        """Type-7 quantiles over each set's replicates of the population
+        prevalence sums[case_c] / sums[at_risk] at tspan indices k0..k0+nk-1.
+        Returns a float32 torch tensor (sets, nk, len(probs)) on the device."""
+        import torch
+        mask = 0
+        for c in at_risk:
+            mask |= 1 << int(c)
+        p = _c(probs, np.float64)
+        sets = self.runs // replicates
+        out = torch.empty((sets, nk, p.size), dtype=torch.float32, device="cuda")
+        rc = self._lib.siminf_prevalence_quantiles(self._h, case_c, mask, replicates, k0, nk, _ptr(p), p.size,
+                                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(hip_stream))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_prevalence_quantiles")
+        return out
+
+
+def header_symbols(header_path: str) -> list:
+    """Names of the functions include/siminf.h declares."""
+    import re
+    text = open(header_path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(siminf_[a-z_0-9]+)\s*\(", text)))

@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer trajectories must be bit-identical, counters equal, and the real
+state V within 1e-12 relative (the same IEEE operations are performed, so
+it is expected to be exact as well)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_01421_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1605_01421_amd import siminf
+    siminf.load()
+    return siminf
+
+
+def _compare(model, ref, run=0, what=""):
+    U, V = model.trajectory(run)
+    if not np.array_equal(U, ref["U"]):
+        bad = np.argwhere(U != ref["U"])
+        raise AssertionError(f"{what}: U differs at {len(bad)} entries, first (t, node, c) = {bad[:3].tolist()}")
+    if V.size:
+        np.testing.assert_allclose(V, ref["V"], rtol=1e-12, atol=0, err_msg=what)
+
+
+def _run_both(lib, spec, seed, stream=0, **opts):
+    _say(spec.name, "seed", seed, "stream", stream, opts)
+    ref = oracle_run(spec, seed, stream)
+    m = lib.Model(spec, **opts)
+    m.run(seed, stream)
+    rc = m.wait()
+    return m, ref, rc
+
+
+def oracle_run(spec, seed, stream):
+    import oracle
+    return oracle.run(spec, seed, stream, nthreads=NTHREADS)
+
+
+def test_plain_sir_100_nodes(lib):
+    spec = W.config0()
+    m, ref, rc = _run_both(lib, spec, 123)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what="sir-100")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], 0)
+    assert m.launch_info()["mode"] == 0
+
+
+@pytest.mark.parametrize("infect", [False, True])
+def test_paper_five_node_event_example(lib, infect):
+    spec = W.sir_event_example(infect)
+    for stream in range(4):
+        m, ref, rc = _run_both(lib, spec, 3, stream)
+        assert rc == 0
+        _compare(m, ref, what=f"five-node stream {stream}")
+        assert m.counters()["events"] == ref["events"]
+        assert m.launch_info()["mode"] == 1
+
+
+@pytest.mark.parametrize("Nn,days,seed", [(257, 40, 1), (1000, 90, 7)])
+def test_sir_with_events_small(lib, Nn, days, seed):
+    spec = W.config1(seed=seed, Nn=Nn, days=days)
+    m, ref, rc = _run_both(lib, spec, 42 + seed, 5)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what=spec.name)
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
+def test_sise_with_events_small(lib):
+    spec = W.config2(seed=4, Nn=700, days=200)
+    m, ref, rc = _run_both(lib, spec, 9, 2)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what=spec.name)
+    assert np.array_equal(m.trajectory()[1], ref["V"]), "phi expected bit-identical"
+
+
+@pytest.mark.parametrize("kind", ["sis", "birth_death", "immigration_death", "sise_noevents"])
+def test_other_models(lib, kind):
+    rng = np.random.default_rng(5)
+    if kind == "sis":
+        spec = W.sis_spec(np.stack([rng.integers(0, 60, 300), rng.integers(0, 5, 300)], 1), np.arange(0, 31),
+                          0.01, 0.2)
+    elif kind == "birth_death":
+        spec = W.birth_death_spec(rng.integers(0, 40, 300), np.arange(0, 21), 0.2, 0.18)
+    elif kind == "immigration_death":
+        spec = W.birth_death_spec(rng.integers(0, 10, 300), np.arange(0, 21), 2.0, 0.3, immigration=True)
+    else:
+        spec = W.sise_spec(np.stack([rng.integers(0, 80, 300), rng.integers(0, 8, 300)], 1),
+                           np.arange(0, 400, 3), 0.0175, 0.1, 1.0, (0.1, 0.12, 0.1, 0.11))
+    m, ref, rc = _run_both(lib, spec, 77, 1)
+    assert rc == 0
+    _compare(m, ref, what=kind)
+    assert m.counters()["transitions"] == ref["transitions"]
+
+
+@pytest.mark.parametrize("opts", [dict(block=64), dict(block=128), dict(block=256), dict(order=1),
+                                  dict(max_blocks=3), dict(block=64, max_blocks=1)])
+def test_launch_shape_does_not_change_bits(lib, opts):
+    spec = W.config1(seed=11, Nn=600, days=50)
+    ref = oracle_run(spec, 5, 0)
+    m = lib.Model(spec, **opts)
+    _say("launch", opts, m.launch_info())
+    m.run(5, 0)
+    assert m.wait() == 0
+    _compare(m, ref, what=str(opts))
+    free = W.config0()
+    ref0 = oracle_run(free, 8, 3)
+    m0 = lib.Model(free, **opts)
+    m0.run(8, 3)
+    assert m0.wait() == 0
+    _compare(m0, ref0, what="free " + str(opts))
+
+
+def test_batch_equals_individual_runs(lib):
+    a = W.sir_spec(np.tile([200, 3, 0], (70, 1)), np.arange(0, 41), 0.3, 0.1)
+    b = W.sise_spec(np.tile([90, 6], (45, 1)), np.arange(0, 41), 0.02, 0.1, 1.0, (0.1, 0.12, 0.1, 0.11))
+    c = W.sir_spec(np.tile([50, 1, 0], (33, 1)), np.arange(0, 41), 0.5, 0.2)
+    batch = [(a, 3), (b, 2), (c, 2)]
+    m = lib.Model(batch)
+    _say("batch full", m.runs)
+    m.run(21, 100)
+    assert m.wait() == 0
+    r = 0
+    for spec, reps in batch:
+        for _ in range(reps):
+            ref = oracle_run(spec, 21, 100 + r)
+            _compare(m, ref, run=r, what=f"batch run {r}")
+            r += 1
+    ms = lib.Model(batch, record=lib.RECORD_SUMS)
+    _say("batch sums")
+    ms.run(21, 100)
+    assert ms.wait() == 0
+    sums = ms.sums()
+    r = 0
+    for spec, reps in batch:
+        for _ in range(reps):
+            ref = oracle_run(spec, 21, 100 + r)
+            want = ref["U"].astype(np.int64).sum(axis=1)
+            assert np.array_equal(sums[r, :, :want.shape[1]], want), r
+            r += 1
+
+
+def test_prevalence_quantiles(lib):
+    import oracle.prevalence as P
+    sets = W.ensemble_sets(seed=9, n_sets=4, replicates=8, days=56, nn_range=(100, 400))
+    m = lib.Model([(s.spec, s.replicates) for s in sets], record=lib.RECORD_SUMS)
+    m.run(1234, 0)
+    assert m.wait() == 0
+    sums = m.sums()
+    q = m.prevalence_quantiles(1, (0, 1), 8, 1, m.ntspan - 1).cpu().numpy()
+    want = P.prevalence_quantiles(sums, 1, (0, 1), 8, 1, m.ntspan - 1, (0.1, 0.5, 0.9))
+    assert np.array_equal(q, want)
+    # and the sums themselves against oracle runs of two sampled replicates
+    for r in (0, 13):
+        spec = sets[r // 8].spec
+        ref = oracle_run(spec, 1234, r)
+        assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1))
+
+
+@pytest.mark.parametrize("case", ["overdraw_e1", "overdraw_e2", "negative_rate"])
+def test_first_error_matches_oracle(lib, case):
+    u0 = np.array([[5, 0, 0], [5, 0, 0], [5, 0, 0]])
+    beta = 0.0
+    if case == "overdraw_e1":
+        rows = [(W.EXIT, 3, 1, 0, 2, 0.0, 0, -1), (W.EXIT, 3, 2, 0, 9, 0.0, 0, -1),
+                (W.EXIT, 3, 0, 0, 6, 0.0, 3, -1)]
+    elif case == "overdraw_e2":
+        rows = [(W.EXTTRANS, 2, 0, 1, 5, 0.0, 0, -1), (W.EXTTRANS, 2, 0, 2, 1, 0.0, 0, -1),
+                (W.EXTTRANS, 2, 1, 2, 11, 0.0, 0, -1)]
+    else:
+        u0 = np.array([[5, 1, 0], [5, 0, 0], [5, 2, 0]])
+        beta = -0.1
+        rows = []
+    spec = W.sir_spec(u0, [0, 1, 2, 3, 4], beta, 0.1, events=W.make_events(rows))
+    m, ref, rc = _run_both(lib, spec, 1, 0)
+    info = m.error_info()
+    assert rc == ref["status"] != 0
+    assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
+
+
+def test_invalid_event_rejected_at_create(lib):
+    spec = W.sir_spec(np.array([[5, 0, 0]]), [0, 1], 0.1, 0.1,
+                      events=W.make_events([(W.EXIT, 1, 0, 0, 1, 0.0, 9, -1)]))
+    with pytest.raises(lib.SiminfError) as e:
+        lib.Model(spec)
+    assert e.value.code == -8
+
+
+def test_trajectory_to_device(lib):
+    import torch
+    spec = W.sir_event_example(True)
+    m, ref, rc = _run_both(lib, spec, 3, 1)
+    U, V = m.trajectory(device=True)
+    assert U.is_cuda and np.array_equal(U.cpu().numpy(), ref["U"])
+
+
+def test_sir_events_full_size(lib):
+    """10,000 nodes, 365 days, the benchmark workload: whole trajectory."""
+    spec = W.config1()
+    _say("config1 full", spec.Nn, len(spec.events["time"]))
+    m, ref, rc = _run_both(lib, spec, 2024, 0)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what="config1 full")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
