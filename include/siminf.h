@@ -174,8 +174,10 @@ int siminf_trajectory(siminf_model *m, int32_t run, int32_t *U, double *V, int32
 int siminf_sums(siminf_model *m, int64_t *sums, int32_t dst_is_device);
 
 /* Counters of the last run: out[0] transitions executed, out[1] node-days
- * simulated, out[2] scheduled events applied.  Waits for the last run. */
-int siminf_counters(siminf_model *m, uint64_t out[3]);
+ * simulated, out[2] scheduled events applied, out[3] SSA steps (Philox
+ * blocks drawn: the transitions plus each node-day's final step that ends
+ * at the day boundary).  Waits for the last run. */
+int siminf_counters(siminf_model *m, uint64_t out[4]);
 
 /* Sizes of a handle: out[0] runs, out[1] total nodes, out[2] Ntspan,
  * out[3] Nc (largest over specs), out[4] Nv (largest), out[5] day steps. */
@@ -191,6 +193,12 @@ int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32
  * out[1] blocks, out[2] mode (0 free-running, 1 day-synchronous),
  * out[3] lanes per node, out[4] order. */
 int siminf_launch_info(const siminf_model *m, int32_t out[5]);
+
+/* Device time of the last run, from HIP events the library records on the
+ * run's stream: out[0] milliseconds of the SSA kernels (all days, events,
+ * post-time steps and records), out[1] of the whole run including the
+ * per-run initialisation.  Waits for the last run. */
+int siminf_timing(siminf_model *m, double out[2]);
 
 /* Frees the handle and its device memory (waits for its last run). */
 void siminf_destroy(siminf_model *m);

@@ -29,7 +29,7 @@ constexpr uint64_t MAX_ORDINAL = 1ull << 38;
 // Per-run control block in device memory, reset before each run.
 struct Ctrl {
     unsigned long long err_key;
-    unsigned long long counters[3];  // transitions, node-days, events
+    unsigned long long counters[4];  // transitions, node-days, events, SSA draws
     unsigned int work[MAX_GROUPS];   // work-queue cursors (free-running mode)
     unsigned int bar_count;          // grid barrier arrivals
     unsigned int bar_gen;            // grid barrier generation (never reset)

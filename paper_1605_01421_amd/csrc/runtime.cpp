@@ -80,8 +80,9 @@ struct siminf_model {
     int status = 0;
     int32_t err_code = 0, err_phase = -1, err_run = -1;
     int64_t err_step = -1, err_index = -1;
-    uint64_t counters[3] = {0, 0, 0};
+    uint64_t counters[4] = {0, 0, 0, 0};
     siminf_options opt{};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // run start, SSA kernels start, run end
 };
 
 namespace {
@@ -549,6 +550,8 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         p.nblocks = blocks;
     }
     if (to_device(m->owned, pos, &m->d_pos)) return hip_fail(m);
+    for (hipEvent_t& e : m->ev)
+        if (hipEventCreate(&e) != hipSuccess) return hip_fail(m);
     return SIMINF_OK;
 }
 
@@ -582,7 +585,7 @@ int finish(siminf_model* m) {
     if (hipStreamSynchronize(m->last_stream) != hipSuccess) return hip_fail(m);
     Ctrl c;
     if (hipMemcpy(&c, m->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess) return hip_fail(m);
-    for (int i = 0; i < 3; ++i) m->counters[i] = c.counters[i];
+    for (int i = 0; i < 4; ++i) m->counters[i] = c.counters[i];
     m->err_code = 0;
     m->err_step = -1;
     m->err_phase = -1;
@@ -616,6 +619,7 @@ int siminf_run(siminf_model* m, uint64_t seed, uint32_t stream_base, void* hip_s
     if ((uint64_t)stream_base + (uint64_t)m->R > (1ull << 24)) return SIMINF_E_ARG;
     if (m->pending) finish(m);
     hipStream_t st = (hipStream_t)hip_stream;
+    if (hipEventRecord(m->ev[0], st) != hipSuccess) return hip_fail(m);
     for (size_t gi = 0; gi < m->groups.size(); ++gi) {
         Group& g = m->groups[gi];
         g.p.seed = seed;
@@ -630,10 +634,12 @@ int siminf_run(siminf_model* m, uint64_t seed, uint32_t stream_base, void* hip_s
         p.sums = m->d_sums;
         if (launch_init(p, 0, 0, 0, true, m->d_sums_init, m->sums_len, st) != hipSuccess) return hip_fail(m);
     }
+    if (hipEventRecord(m->ev[1], st) != hipSuccess) return hip_fail(m);
     for (Group& g : m->groups) {
         if (g.n == 0) continue;
         if (launch_group(g.model, g.p, g.block, g.blocks, g.mode == 1, st) != hipSuccess) return hip_fail(m);
     }
+    if (hipEventRecord(m->ev[2], st) != hipSuccess) return hip_fail(m);
     m->last_stream = st;
     m->pending = true;
     m->ran = true;
@@ -696,10 +702,10 @@ int siminf_sums(siminf_model* m, int64_t* sums, int32_t dst_is_device) {
     return SIMINF_OK;
 }
 
-int siminf_counters(siminf_model* m, uint64_t out[3]) {
+int siminf_counters(siminf_model* m, uint64_t out[4]) {
     if (!m || !out) return SIMINF_E_ARG;
     finish(m);
-    for (int i = 0; i < 3; ++i) out[i] = m->counters[i];
+    for (int i = 0; i < 4; ++i) out[i] = m->counters[i];
     return SIMINF_OK;
 }
 
@@ -740,9 +746,23 @@ int siminf_launch_info(const siminf_model* m, int32_t out[5]) {
     return SIMINF_OK;
 }
 
+int siminf_timing(siminf_model* m, double out[2]) {
+    if (!m || !out || !m->ran) return SIMINF_E_ARG;
+    finish(m);
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, m->ev[1], m->ev[2]) != hipSuccess ||
+        hipEventElapsedTime(&b, m->ev[0], m->ev[2]) != hipSuccess)
+        return SIMINF_E_DEVICE;
+    out[0] = a;
+    out[1] = b;
+    return SIMINF_OK;
+}
+
 void siminf_destroy(siminf_model* m) {
     if (!m) return;
     if (m->pending) finish(m);
+    for (hipEvent_t e : m->ev)
+        if (e) (void)hipEventDestroy(e);
     for (void* p : m->owned) (void)hipFree(p);
     delete m;
 }

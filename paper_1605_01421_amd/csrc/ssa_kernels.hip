@@ -66,7 +66,8 @@ __device__ __forceinline__ bool rate_ok(double w) {
 template <class M>
 __device__ __forceinline__ int ssa_to_boundary(const KParams& p, Node<M>& s, double t, double T,
                                                uint32_t day_word, uint32_t node, uint32_t stream,
-                                               unsigned long long& transitions) {
+                                               unsigned long long& transitions,
+                                               unsigned long long& draws) {
     static_assert(M::NT == 2, "kernels are written for two-transition models");
     double w0 = M::template rate<0>(s.u, s.v, s.ld, s.gd);
     double w1 = M::template rate<1>(s.u, s.v, s.ld, s.gd);
@@ -79,6 +80,7 @@ __device__ __forceinline__ int ssa_to_boundary(const KParams& p, Node<M>& s, dou
         lam = lam + w1;
         if (!(lam > 0.0)) break;
         if (step == STEP_LIMIT) return E_BAD_RATE;
+        draws += 1;
         const Block4 r = philox10(k0, k1, step, day_word, node, tag);
         const double r1 = open_uniform(r.x, r.y);
         const double r2 = open_uniform(r.z, r.w);
@@ -221,14 +223,16 @@ __device__ __forceinline__ void record(const KParams& p, const Node<M>& s, int k
 }
 
 __device__ __forceinline__ void add_counters(Ctrl* c, unsigned long long tr, unsigned long long nd,
-                                             unsigned long long ev) {
+                                             unsigned long long ev, unsigned long long dr) {
     tr = wave_sum(tr);
     nd = wave_sum(nd);
     ev = wave_sum(ev);
+    dr = wave_sum(dr);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         if (tr) atomicAdd(&c->counters[0], tr);
         if (nd) atomicAdd(&c->counters[1], nd);
         if (ev) atomicAdd(&c->counters[2], ev);
+        if (dr) atomicAdd(&c->counters[3], dr);
     }
 }
 
@@ -238,7 +242,7 @@ __device__ __forceinline__ void add_counters(Ctrl* c, unsigned long long tr, uns
 template <class M>
 __global__ void __launch_bounds__(256) free_kernel(KParams p) {
     const int lane = threadIdx.x & (WAVE - 1);
-    unsigned long long n_tr = 0, n_nd = 0, n_ev = 0;
+    unsigned long long n_tr = 0, n_nd = 0, n_ev = 0, n_dr = 0;
     for (;;) {
         unsigned chunk = 0;
         if (lane == 0) chunk = atomicAdd(&p.ctrl->work[p.group], 1u);
@@ -269,7 +273,7 @@ __global__ void __launch_bounds__(256) free_kernel(KParams p) {
             const double T = (double)day;
             const double t = b == 0 ? p.t0 : T - 1.0;
             if (active && !dead) {
-                int rc = ssa_to_boundary<M>(p, s, t, T, (uint32_t)(int32_t)day, node, stream, n_tr);
+                int rc = ssa_to_boundary<M>(p, s, t, T, (uint32_t)(int32_t)day, node, stream, n_tr, n_dr);
                 if (rc) {
                     raise_error(p.ctrl, b, PH_SSA, ord, rc);
                     dead = true;
@@ -293,7 +297,7 @@ __global__ void __launch_bounds__(256) free_kernel(KParams p) {
             record<M>(p, s, k, run, active, p.rec_off[b], p.rec_off[b + 1]);
         }
     }
-    add_counters(p.ctrl, n_tr, n_nd, n_ev);
+    add_counters(p.ctrl, n_tr, n_nd, n_ev, n_dr);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,7 +341,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nthreads = gridDim.x * blockDim.x;
     const int wave_base = gtid - lane;
-    unsigned long long n_tr = 0, n_nd = 0, n_ev = 0;
+    unsigned long long n_tr = 0, n_nd = 0, n_ev = 0, n_dr = 0;
     unsigned epoch = 0;
     for (int b = 0; b < p.nb; ++b) {
         const bool stop = error_step(p.ctrl) < (uint64_t)b;
@@ -357,7 +361,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
                 const int64_t ord = p.node_ord[k];
                 bool dead = false;
                 int rc = ssa_to_boundary<M>(p, s, t, T, (uint32_t)(int32_t)day, (uint32_t)p.node_idx[k],
-                                            stream, n_tr);
+                                            stream, n_tr, n_dr);
                 if (rc) {
                     raise_error(p.ctrl, b, PH_SSA, ord, rc);
                     dead = true;
@@ -445,7 +449,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
             record<M>(p, s, k, run, active, p.rec_off[b], p.rec_off[b + 1]);
         }
     }
-    add_counters(p.ctrl, n_tr, n_nd, n_ev);
+    add_counters(p.ctrl, n_tr, n_nd, n_ev, n_dr);
     if (gtid == 0 && __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         raise_error(p.ctrl, 0, 0, 0, E_DEVICE);
 }
@@ -459,7 +463,7 @@ __global__ void init_kernel(KParams p, int nc, int nv, int first_rec, int reset_
     const int nthreads = gridDim.x * blockDim.x;
     if (reset_ctrl && gtid == 0) {
         p.ctrl->err_key = NO_ERROR;
-        for (int i = 0; i < 3; ++i) p.ctrl->counters[i] = 0;
+        for (int i = 0; i < 4; ++i) p.ctrl->counters[i] = 0;
         for (int i = 0; i < MAX_GROUPS; ++i) p.ctrl->work[i] = 0;
         p.ctrl->bar_count = 0;
         p.ctrl->abort = 0;

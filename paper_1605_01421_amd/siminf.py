@@ -61,6 +61,7 @@ SIGNATURES = {
     "siminf_shape": (ctypes.c_int, [_P, _P]),
     "siminf_error_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "siminf_launch_info": (ctypes.c_int, [_P, _P]),
+    "siminf_timing": (ctypes.c_int, [_P, _P]),
     "siminf_destroy": (None, [_P]),
     "siminf_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "siminf_prevalence_quantiles": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
@@ -224,11 +225,19 @@ class Model:
                     phase=phase.value, index=index.value, run=run.value)
 
     def counters(self) -> dict:
-        out = np.zeros(3, dtype=np.uint64)
+        out = np.zeros(4, dtype=np.uint64)
         rc = self._lib.siminf_counters(self._h, _ptr(out))
         if rc != SIMINF_OK:
             raise SiminfError(rc, "siminf_counters")
-        return dict(transitions=int(out[0]), node_days=int(out[1]), events=int(out[2]))
+        return dict(transitions=int(out[0]), node_days=int(out[1]), events=int(out[2]), draws=int(out[3]))
+
+    def timing(self) -> dict:
+        """Milliseconds of the last run's SSA kernels and of the whole run."""
+        out = np.zeros(2, dtype=np.float64)
+        rc = self._lib.siminf_timing(self._h, _ptr(out))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_timing")
+        return dict(kernel_ms=float(out[0]), run_ms=float(out[1]))
 
     def launch_info(self) -> dict:
         out = np.zeros(5, dtype=np.int32)
