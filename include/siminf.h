@@ -127,9 +127,16 @@ typedef struct {
     int32_t record;    /* SIMINF_RECORD_FULL (default) or SIMINF_RECORD_SUMS */
     int32_t block;     /* threads per workgroup, multiple of 64 up to 1024; 0 = tuned */
     int32_t order;     /* lane order: 0 = binned by expected work (default), 1 = input order */
-    int32_t lanes;     /* lanes cooperating on one node: 1 (default), 2, 4 or 8 */
+    int32_t lanes;     /* lanes per node: 0 auto, 1 one lane for every node, 64 the
+                          heaviest nodes get a whole wavefront (its 64 lanes draw
+                          64 steps' random numbers at once) */
     int32_t max_blocks;/* cap on the number of workgroups (0 = occupancy limit) */
-    int32_t reserved[3];
+    int32_t pipeline;  /* 0 auto, 1 overlap each step's random numbers with the
+                          previous step (latency), 2 off (throughput) */
+    int32_t mode;      /* runs with external transfers: 0 auto, 1 grid-barrier
+                          kernel, 2 dataflow kernel (node state in registers) */
+    int32_t wide;      /* with lanes = 64: how many of the heaviest nodes get a
+                          wavefront (0 = chosen from the expected work) */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;
@@ -189,10 +196,19 @@ int siminf_shape(const siminf_model *m, int64_t out[6]);
 int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32_t *phase,
                       int64_t *index, int32_t *run);
 
-/* Launch configuration chosen for the handle: out[0] threads per block,
- * out[1] blocks, out[2] mode (0 free-running, 1 day-synchronous),
- * out[3] lanes per node, out[4] order. */
-int siminf_launch_info(const siminf_model *m, int32_t out[5]);
+/* Launch configuration chosen for the handle (its first model group):
+ * out[0] threads per block, out[1] blocks, out[2] kernel (0 free-running,
+ * 1 grid-barrier, 2 dataflow), out[3] pipelining on/off, out[4] order,
+ * out[5] nodes carried by a whole wavefront. */
+int siminf_launch_info(const siminf_model *m, int32_t out[6]);
+
+/* Autotuner: runs the model `repeats` times for each candidate launch shape
+ * (threads per block 64/128/256; none, half, the default or twice the
+ * default number of wavefront-wide nodes; pipelining on/off), on hip_stream
+ * with seeds seed, seed+1, ..., and keeps the shape with the smallest median
+ * SSA-kernel time (written to *best_ms if not NULL).  Every shape gives
+ * bit-identical results; the handle's recorded results are overwritten. */
+int siminf_autotune(siminf_model *m, uint64_t seed, int32_t repeats, void *hip_stream, double *best_ms);
 
 /* Device time of the last run, from HIP events the library records on the
  * run's stream: out[0] milliseconds of the SSA kernels (all days, events,

@@ -14,6 +14,9 @@ constexpr int MAX_GROUPS = 8; // one group per built-in model present in a batch
 // phases of one unit of time, in the order of Appendix A
 enum Phase { PH_SSA = 0, PH_E1 = 1, PH_E2 = 2, PH_PTS = 3 };
 
+// kernel modes
+enum Mode { MODE_FREE = 0, MODE_BARRIER = 1, MODE_FLOW = 2 };
+
 // Error key: ordered like the serial algorithm (step, phase, global ordinal),
 // code in the low bits.  The global ordinal of a node is its input position
 // across runs; of an event, its position in the concatenated event tables.
@@ -32,30 +35,36 @@ struct Ctrl {
     unsigned long long counters[4];  // transitions, node-days, events, SSA draws
     unsigned int work[MAX_GROUPS];   // work-queue cursors (free-running mode)
     unsigned int bar_count;          // grid barrier arrivals
-    unsigned int bar_gen;            // grid barrier generation (never reset)
-    unsigned int abort;              // set when a barrier wait timed out
+    unsigned int abort;              // set when a wait exceeded its spin limit
+    unsigned int e2done;             // dataflow mode: steps whose transfers are applied
     unsigned int pad;
 };
 
-// Scheduled events, structure of arrays, sorted for their consumer.
+// One scheduled event, packed for a single 16-byte load:
+//   x = time, y = type | select mask << 2 | target(c) << (6 + 2c), z = n,
+//   w = input index within its spec (the sampling RNG's identity)
+// where mask bit c selects compartment c and target(c) is where a sampled
+// individual of compartment c goes (c + N[c, shift], or c without shift).
+inline int32_t pack_event(int type, uint32_t mask, const int* target, int nc) {
+    uint32_t w = (uint32_t)type | (mask << 2);
+    for (int c = 0; c < nc; ++c) w |= (uint32_t)target[c] << (6 + 2 * c);
+    return (int32_t)w;
+}
+
 struct EventSoA {
-    const int32_t* time;
-    const int32_t* type;
-    const int32_t* n;
-    const int32_t* select;
-    const int32_t* shift;
-    const int32_t* id;       // input index within its spec (RNG identity)
+    const int4* rec;         // packed records
+    const double* prop;      // proportion (used when n == 0)
     const int64_t* ordinal;  // global ordinal for the error key
-    const double* prop;
-    const int32_t* node;     // group-local node of the event (E2: source)
-    const int32_t* dest;     // group-local destination (E2 only)
+    const int32_t* node;     // barrier mode E2: group-local source node
+    const int32_t* dest;     // barrier mode E2: group-local destination
+    const int32_t* run;      // E2: run of the event (its sampling stream is stream_base + run)
 };
 
 struct KParams {
     int32_t n;        // nodes in the group
     int32_t nb;       // number of unit-time steps
     int32_t ntspan;
-    int32_t mode;     // 0 free-running, 1 day-synchronous
+    int32_t mode;     // Mode
     int64_t T1;       // first day boundary
     double t0;        // start time
     uint64_t seed;
@@ -63,13 +72,10 @@ struct KParams {
     int32_t ngd;
     int32_t S[MAX_NC * MAX_NT];  // state-change matrix, column-major
     uint32_t Gmask[MAX_NT];      // bit k of Gmask[j]: recompute rate k after transition j
-    int32_t ecols, ncols;
-    const uint32_t* Emask;       // [ecols] bit c: compartment c selected
-    const int32_t* Nshift;       // [ncols][MAX_NC]
     const int32_t* rec_off;      // [nb+1] tspan indices written after step b
     const int32_t* u0;           // [nc][n]
     const double* v0;            // [nv][n]
-    int32_t* u;                  // live state [nc][n] (day-synchronous mode)
+    int32_t* u;                  // live state [nc][n] (barrier / dataflow modes)
     double* v;                   // [nv][n]
     const double* ld;            // [nld][n]
     const int32_t* node_run;     // [n] run of each node
@@ -78,11 +84,18 @@ struct KParams {
     const double* gdata;         // [nspec][ngd]
     const int32_t* run_spec;     // [runs]
     const int32_t* e1_off;       // [n+1]
-    int32_t* e1_cur;             // [n]
+    int32_t* e1_cur;             // [n] (barrier mode)
     EventSoA e1;
     const int32_t* e2_step;      // [nb+1] level range of each step
     const int32_t* e2_lvl;       // [levels+1] event range of each level
     EventSoA e2;
+    const int32_t* e2n_off;      // dataflow: [n+1] per node, its external transfers
+    const int4* e2n_rec;         //           packed record of each (sources sample from it)
+    const int4* e2n_item;        //           x = event index, y = step, z = role (0 source,
+                                 //           1 destination, 2 both), w = run of the event
+    unsigned long long* mail;    // dataflow: [n_e2] counts a transfer delivers (0 = not yet)
+    int32_t* mail_big;           //           [n_e2][MAX_NC] counts too large to pack
+    int32_t n_e2;
     int32_t record;              // 0 full, 1 sums
     int32_t sums_nc;             // compartment stride of the sums array
     int32_t* U;                  // [ntspan][nc][n]
@@ -92,18 +105,19 @@ struct KParams {
     int32_t group;
     int32_t nchunks;             // 64-node chunks (free-running work queue)
     int32_t nblocks;
-    int32_t pad;
+    int32_t pipeline;            // 1: overlap the next step's random numbers with this step
+    int32_t nbig;                // the first nbig nodes each get a whole wavefront
+    int32_t pad2;
 };
 
 // Launchers implemented in ssa_kernels.hip.
 hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st);
-hipError_t launch_group(int model, const KParams& p, int block, int blocks, bool cooperative,
+hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem,
                         hipStream_t st);
-int max_blocks_per_cu(int model, int mode, int block);
-hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n,
-                         int ntspan, const int32_t* pos, int nn, int32_t* Uo, double* Vo,
-                         hipStream_t st);
+int max_blocks_per_cu(int model, int mode, int pipeline, int block, size_t shmem);
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan,
+                         const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
 hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,
                              int case_c, uint32_t mask, int reps, int k0, int nk,
                              const double* probs, int nq, float* out, hipStream_t st);

@@ -12,6 +12,8 @@ namespace siminf {
 
 enum ModelId { M_SIR = 0, M_SIS = 1, M_SISE = 2, M_BIRTH_DEATH = 3, M_IMMIGRATION_DEATH = 4 };
 
+__device__ __forceinline__ double pick(bool c, double a, double b) { return c ? a : b; }
+
 // SIR (eq. SIR): S -> I at beta S I / (S + I + R), 0 for an empty node
 // (Appendix C listing); I -> R at gamma I.  gdata = (beta, gamma).
 struct ModelSIR {
@@ -73,8 +75,10 @@ struct ModelSISe {
         int64_t r = (day - 1) % 365;
         if (r < 0) r += 365;
         const double doy = (double)(r + 1);
-        const double decay = doy <= ld[0] ? gd[3] : doy <= ld[1] ? gd[4]
-                           : doy <= ld[2] ? gd[5] : doy <= ld[3] ? gd[6] : gd[3];
+        // selects on values (not on array elements) keep the node in registers
+        const double decay = pick(doy <= ld[0], gd[3],
+                                  pick(doy <= ld[1], gd[4],
+                                       pick(doy <= ld[2], gd[5], pick(doy <= ld[3], gd[6], gd[3]))));
         const double kept = v[0] * (1.0 - decay);
         const int32_t total = u[0] + u[1];
         const double shed = total > 0 ? (gd[2] * (double)u[1]) / (double)total : 0.0;

@@ -34,8 +34,10 @@ struct Group {
     int n = 0;
     int mode = 0;  // 0 free-running, 1 day-synchronous
     int block = 256, blocks = 1;
+    size_t shmem = 0;
     KParams p{};
     int64_t n_e1 = 0, n_e2 = 0, n_levels = 0;
+    std::vector<int64_t> work;  // expected work of each node, internal (descending) order
 };
 
 template <class T>
@@ -159,6 +161,89 @@ bool same_matrix(const int32_t* a, const int32_t* b, size_t n) {
     return n == 0 || std::memcmp(a, b, sizeof(int32_t) * n) == 0;
 }
 
+int device_cus(const siminf_model* m) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess) return 0;
+    return cus;
+}
+
+// Heaviest nodes worth a whole wavefront each.  A wide node runs its steps
+// about twice as fast as a node sharing its wavefront with 63 others but
+// occupies 64 lanes, so only nodes that would otherwise set the critical path
+// qualify: expected work above a fifth of the heaviest node's and above the
+// share of the whole run one lane would get if the work were spread evenly
+// over 34,560 lanes (the measured throughput of the device in lane-steps per
+// lane-step time).  Needs the binned (work-sorted) node order.
+int default_wide(const siminf_model* m, const Group& g) {
+    if (m->opt.lanes == 1 || g.n == 0 || m->opt.order == 1) return 0;
+    if (m->opt.lanes == 64 && m->opt.wide > 0) return std::min(m->opt.wide, g.n);
+    const int64_t top = g.work[0];
+    long double total = 0;
+    for (int64_t w : g.work) total += (long double)w;
+    const long double cut = std::max((long double)top / 5.0L, total / 34560.0L);
+    int nb = 0;
+    while (nb < g.n && nb < 4096 && (long double)g.work[nb] > cut) ++nb;
+    return nb;
+}
+
+// Kernel and launch shape of one group.  want_mode applies to groups with
+// external transfers: 0 auto (dataflow if every node wavefront and the worker
+// fit on the device at once, else grid barrier), 1 barrier, 2 dataflow.
+int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode) {
+    KParams& p = g.p;
+    const int n = g.n, nc = g.shape.nc;
+    const int cus = device_cus(m);
+    if (cus <= 0) return SIMINF_E_DEVICE;
+    nbig = std::max(0, std::min(nbig, n));
+    // pipelining pays where lanes are scarce (latency-bound runs); with many
+    // waves per SIMD the extra, unused last draw of each node-day only costs
+    const int simd_lanes = cus * 4 * WAVE;
+    p.pipeline = pipeline == 1 ? 1 : pipeline == 2 ? 0 : (n <= simd_lanes ? 1 : 0);
+    if (block == 0) block = g.n_e2 > 0 ? 64 : 256;
+    const int wpb = block / WAVE;
+    int mode = MODE_FREE, blocks = 0;
+    size_t shmem = 0;
+    if (g.n_e2 > 0) {
+        if (want_mode == 0 || want_mode == 2) {
+            const int per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, block, 0);
+            int nb = nbig;
+            auto need = [&](int k) { return (k + (n - k + WAVE - 1) / WAVE + wpb - 1) / wpb; };
+            while (nb > 0 && per_cu > 0 && need(nb) > per_cu * cus) nb /= 2;
+            if (per_cu > 0 && need(nb) <= per_cu * cus) {
+                mode = MODE_FLOW;
+                nbig = nb;
+                blocks = std::max(1, need(nb));
+            } else if (want_mode == 2) {
+                return SIMINF_E_UNSUPPORTED;
+            }
+        }
+        if (mode != MODE_FLOW) {
+            mode = MODE_BARRIER;
+            shmem = 0;
+            nbig = 0;
+            const int per_cu = max_blocks_per_cu(g.model, MODE_BARRIER, p.pipeline, block, 0);
+            if (per_cu <= 0) return SIMINF_E_DEVICE;
+            blocks = std::max(1, std::min(per_cu * cus, (n + block - 1) / block));
+            if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
+        }
+    } else {
+        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, p.pipeline, block, 0);
+        if (per_cu <= 0) return SIMINF_E_DEVICE;
+        const int chunks = nbig + (n - nbig + WAVE - 1) / WAVE;
+        blocks = std::max(1, std::min(per_cu * cus, (chunks + wpb - 1) / wpb));
+        if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
+    }
+    g.mode = mode;
+    p.mode = mode;
+    p.nbig = nbig;
+    p.nchunks = nbig + (n - nbig + WAVE - 1) / WAVE;
+    g.block = block;
+    g.blocks = blocks;
+    g.shmem = shmem;
+    p.nblocks = blocks;
+    return SIMINF_OK;
+}
+
 int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const siminf_options* opt,
                 siminf_model** out) {
     if (!out) return SIMINF_E_ARG;
@@ -176,7 +261,11 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
-    if (m->opt.lanes != 0 && m->opt.lanes != 1) {
+    if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2) {
+        set_create_error(m, SIMINF_E_ARG, -1, -1);
+        return SIMINF_E_ARG;
+    }
+    if (m->opt.lanes != 0 && m->opt.lanes != 1 && m->opt.lanes != 64) {
         set_create_error(m, SIMINF_E_UNSUPPORTED, -1, -1);
         return SIMINF_E_UNSUPPORTED;
     }
@@ -340,6 +429,8 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                              [](const NodeRef& a, const NodeRef& b) { return a.work > b.work; });
         const int n = (int)nodes.size();
         g.n = n;
+        g.work.resize(n);
+        for (int k = 0; k < n; ++k) g.work[k] = nodes[k].work;
         std::vector<int32_t> u0s((size_t)nc * n), node_run(n), node_idx(n);
         std::vector<double> v0s((size_t)nv * n), lds((size_t)nld * n);
         std::vector<int64_t> node_ord(n);
@@ -433,37 +524,85 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         g.n_e1 = (int64_t)e1.size();
         g.n_e2 = (int64_t)order2.size();
         g.n_levels = (int64_t)e2_lvl.size() - 1;
-        g.mode = g.n_e2 > 0 ? 1 : 0;
 
+        // per-node lists of external transfers in key order, for the dataflow
+        // kernel: the source samples, the destination receives (a transfer from
+        // a node to itself is one item with both roles)
+        std::vector<int32_t> e2n_off(n + 1, 0);
+        std::vector<int4> e2n_item;
+        std::vector<size_t> e2n_src;  // index into order2 of each item (for its record)
+        {
+            std::vector<std::vector<std::pair<int4, size_t>>> per(n);
+            size_t j = 0;
+            for (int b = 0; b < m->nb; ++b) {
+                const size_t jend = (size_t)e2_lvl[e2_step[b + 1]];
+                for (; j < jend; ++j) {
+                    const Ev& x = e2k[order2[j]];
+                    const siminf_spec& s = S_of(x.run);
+                    const int src = local(x.run, s.ev_node[x.e]);
+                    const int dst = local(x.run, s.ev_dest[x.e]);
+                    per[src].push_back({make_int4((int)j, b, src == dst ? 2 : 0, x.run), j});
+                    if (dst != src) per[dst].push_back({make_int4((int)j, b, 1, x.run), j});
+                }
+            }
+            // within a node, the items must follow the serial (key) order, which
+            // the level order of a step does not keep: sort by the event's key
+            for (int k = 0; k < n; ++k) {
+                std::stable_sort(per[k].begin(), per[k].end(), [&](const auto& A, const auto& B) {
+                    const Ev& xa = e2k[order2[A.second]];
+                    const Ev& xb = e2k[order2[B.second]];
+                    return std::make_tuple(A.first.y, S_of(xa.run).ev_time[xa.e], xa.run, xa.e) <
+                           std::make_tuple(B.first.y, S_of(xb.run).ev_time[xb.e], xb.run, xb.e);
+                });
+                e2n_off[k + 1] = e2n_off[k] + (int32_t)per[k].size();
+                for (auto& it : per[k]) {
+                    e2n_item.push_back(it.first);
+                    e2n_src.push_back(it.second);
+                }
+            }
+        }
+
+        // packed event records (select mask and shift targets resolved here)
+        std::vector<int4> e2_rec_host;
         auto fill = [&](const std::vector<Ev>& list, const std::vector<size_t>* perm, EventSoA* soa,
-                        bool with_dest) -> bool {
+                        bool transfers) -> bool {
             const size_t cnt = perm ? perm->size() : list.size();
-            std::vector<int32_t> time(cnt), type(cnt), nn(cnt), sel(cnt), sh(cnt), id(cnt), nd(cnt), ds(cnt);
+            std::vector<int4> rec(cnt);
+            std::vector<int32_t> nd(transfers ? cnt : 0), ds(transfers ? cnt : 0), rn(transfers ? cnt : 0);
             std::vector<double> prop(cnt);
             std::vector<int64_t> ord(cnt);
             for (size_t j = 0; j < cnt; ++j) {
                 const Ev& x = perm ? list[(*perm)[j]] : list[j];
                 const siminf_spec& s = S_of(x.run);
-                time[j] = s.ev_time[x.e];
-                type[j] = s.ev_type[x.e];
-                nn[j] = s.ev_n[x.e];
-                sel[j] = s.ev_select[x.e];
-                sh[j] = s.ev_shift[x.e];
-                id[j] = x.e;
+                const int sel = s.ev_select[x.e], q = s.ev_shift[x.e];
+                uint32_t mask = 0;
+                int target[MAX_NC] = {0, 1, 2, 3};
+                for (int c = 0; c < nc; ++c) {
+                    if (s.E[(size_t)sel * nc + c]) mask |= 1u << c;
+                    if (q >= 0 && s.ev_type[x.e] != SIMINF_ENTER) target[c] = c + s.N[(size_t)q * nc + c];
+                    if (target[c] < 0 || target[c] >= nc) target[c] = c;  // unselected rows are never used
+                }
+                rec[j] = make_int4(s.ev_time[x.e], pack_event(s.ev_type[x.e], mask, target, nc), s.ev_n[x.e], x.e);
                 prop[j] = s.ev_prop[x.e];
                 ord[j] = m->runs[x.run].eoff + x.e;
-                nd[j] = local(x.run, s.ev_node[x.e]);
-                ds[j] = with_dest ? local(x.run, s.ev_dest[x.e]) : 0;
+                if (transfers) {
+                    nd[j] = local(x.run, s.ev_node[x.e]);
+                    ds[j] = local(x.run, s.ev_dest[x.e]);
+                    rn[j] = x.run;
+                }
             }
-            int32_t *a1, *a2, *a3, *a4, *a5, *a6, *a7, *a8;
-            double* a9;
-            int64_t* a10;
-            if (to_device(m->owned, time, &a1) || to_device(m->owned, type, &a2) || to_device(m->owned, nn, &a3) ||
-                to_device(m->owned, sel, &a4) || to_device(m->owned, sh, &a5) || to_device(m->owned, id, &a6) ||
-                to_device(m->owned, nd, &a7) || to_device(m->owned, ds, &a8) || to_device(m->owned, prop, &a9) ||
-                to_device(m->owned, ord, &a10))
+            int4* a_rec;
+            double* a_prop;
+            int64_t* a_ord;
+            int32_t *a_nd = nullptr, *a_ds = nullptr, *a_rn = nullptr;
+            if (to_device(m->owned, rec, &a_rec) || to_device(m->owned, prop, &a_prop) ||
+                to_device(m->owned, ord, &a_ord))
                 return false;
-            *soa = EventSoA{a1, a2, a3, a4, a5, a6, a10, a9, a7, a8};
+            if (transfers && (to_device(m->owned, nd, &a_nd) || to_device(m->owned, ds, &a_ds) ||
+                              to_device(m->owned, rn, &a_rn)))
+                return false;
+            *soa = EventSoA{a_rec, a_prop, a_ord, a_nd, a_ds, a_rn};
+            if (transfers) e2_rec_host = rec;
             return true;
         };
         KParams& p = g.p;
@@ -471,7 +610,6 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         p.n = n;
         p.nb = m->nb;
         p.ntspan = m->ntspan;
-        p.mode = g.mode;
         p.T1 = m->T1;
         p.t0 = m->t0;
         p.ngd = std::max(ngd_max, 1);
@@ -482,28 +620,24 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 if (sp.G[k + (size_t)j * g.shape.nt]) mask |= 1u << k;
             p.Gmask[j] = mask;
         }
-        std::vector<uint32_t> emask(std::max(sp.Ecols, 1), 0u);
-        for (int s = 0; s < sp.Ecols; ++s)
-            for (int c = 0; c < nc; ++c)
-                if (sp.E[(size_t)s * nc + c]) emask[s] |= 1u << c;
-        std::vector<int32_t> nshift((size_t)std::max(sp.Ncols, 1) * MAX_NC, 0);
-        for (int q = 0; q < sp.Ncols; ++q)
-            for (int c = 0; c < nc; ++c) nshift[(size_t)q * MAX_NC + c] = sp.N[(size_t)q * nc + c];
-        p.ecols = sp.Ecols;
-        p.ncols = sp.Ncols;
-        uint32_t* d_emask;
-        int32_t *d_nshift, *d_u0, *d_nrun, *d_nidx, *d_e1off, *d_e2step, *d_e2lvl;
+        int32_t *d_u0, *d_nrun, *d_nidx, *d_e1off, *d_e2step, *d_e2lvl, *d_e2noff;
         double *d_v0, *d_ld;
         int64_t* d_nord;
-        if (to_device(m->owned, emask, &d_emask) || to_device(m->owned, nshift, &d_nshift) ||
-            to_device(m->owned, u0s, &d_u0) || to_device(m->owned, v0s, &d_v0) || to_device(m->owned, lds, &d_ld) ||
+        if (to_device(m->owned, u0s, &d_u0) || to_device(m->owned, v0s, &d_v0) || to_device(m->owned, lds, &d_ld) ||
             to_device(m->owned, node_run, &d_nrun) || to_device(m->owned, node_idx, &d_nidx) ||
             to_device(m->owned, node_ord, &d_nord) || to_device(m->owned, e1_off, &d_e1off) ||
-            to_device(m->owned, e2_step, &d_e2step) || to_device(m->owned, e2_lvl, &d_e2lvl))
+            to_device(m->owned, e2_step, &d_e2step) || to_device(m->owned, e2_lvl, &d_e2lvl) ||
+            to_device(m->owned, e2n_off, &d_e2noff))
             return hip_fail(m);
         if (!fill(e1, nullptr, &p.e1, false) || !fill(e2k, &order2, &p.e2, true)) return hip_fail(m);
-        p.Emask = d_emask;
-        p.Nshift = d_nshift;
+        {
+            std::vector<int4> e2n_rec(e2n_item.size());
+            for (size_t i = 0; i < e2n_item.size(); ++i) e2n_rec[i] = e2_rec_host[e2n_src[i]];
+            int4 *d_item, *d_nrec;
+            if (to_device(m->owned, e2n_item, &d_item) || to_device(m->owned, e2n_rec, &d_nrec)) return hip_fail(m);
+            p.e2n_item = d_item;
+            p.e2n_rec = d_nrec;
+        }
         p.rec_off = d_rec_off;
         p.u0 = d_u0;
         p.v0 = d_v0;
@@ -516,11 +650,8 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         p.e1_off = d_e1off;
         p.e2_step = d_e2step;
         p.e2_lvl = d_e2lvl;
-        if (g.mode == 1) {
-            if (alloc_device(m->owned, (size_t)nc * n, &p.u) || alloc_device(m->owned, (size_t)std::max(nv, 1) * n, &p.v) ||
-                alloc_device(m->owned, (size_t)n, &p.e1_cur))
-                return hip_fail(m);
-        }
+        p.e2n_off = d_e2noff;
+        p.n_e2 = (int32_t)order2.size();
         p.record = m->record;
         p.sums_nc = m->ncmax;
         p.sums = m->d_sums;
@@ -531,23 +662,18 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         }
         p.ctrl = m->d_ctrl;
         p.group = (int)gi;
-        p.nchunks = (n + WAVE - 1) / WAVE;
-
-        // launch shape
-        int block = m->opt.block;
-        if (block == 0) block = g.mode == 1 ? 64 : 256;
-        const int per_cu = max_blocks_per_cu(g.model, g.mode, block);
-        if (per_cu <= 0) return hip_fail(m);
-        const int cap = per_cu * cus;
-        int blocks;
-        if (g.mode == 1)
-            blocks = std::max(1, std::min(cap, (n + block - 1) / block));
-        else
-            blocks = std::max(1, std::min(cap, (p.nchunks + block / WAVE - 1) / (block / WAVE)));
-        if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
-        g.block = block;
-        g.blocks = blocks;
-        p.nblocks = blocks;
+        if (g.n_e2 > 0) {
+            // live state for the transfer kernels (both variants)
+            if (alloc_device(m->owned, (size_t)nc * n, &p.u) || alloc_device(m->owned, (size_t)std::max(nv, 1) * n, &p.v) ||
+                alloc_device(m->owned, (size_t)n, &p.e1_cur) || alloc_device(m->owned, (size_t)p.n_e2, &p.mail) ||
+                alloc_device(m->owned, (size_t)p.n_e2 * MAX_NC, &p.mail_big))
+                return hip_fail(m);
+        }
+        const int rc = configure(m, g, m->opt.block, default_wide(m, g), m->opt.pipeline, m->opt.mode);
+        if (rc) {
+            set_create_error(m, rc, -1, -1);
+            return rc;
+        }
     }
     if (to_device(m->owned, pos, &m->d_pos)) return hip_fail(m);
     for (hipEvent_t& e : m->ev)
@@ -637,7 +763,7 @@ int siminf_run(siminf_model* m, uint64_t seed, uint32_t stream_base, void* hip_s
     if (hipEventRecord(m->ev[1], st) != hipSuccess) return hip_fail(m);
     for (Group& g : m->groups) {
         if (g.n == 0) continue;
-        if (launch_group(g.model, g.p, g.block, g.blocks, g.mode == 1, st) != hipSuccess) return hip_fail(m);
+        if (launch_group(g.model, g.p, g.block, g.blocks, g.shmem, st) != hipSuccess) return hip_fail(m);
     }
     if (hipEventRecord(m->ev[2], st) != hipSuccess) return hip_fail(m);
     m->last_stream = st;
@@ -731,18 +857,69 @@ int siminf_error_info(const siminf_model* m, int32_t* code, int64_t* step, int32
     return SIMINF_OK;
 }
 
-int siminf_launch_info(const siminf_model* m, int32_t out[5]) {
+int siminf_launch_info(const siminf_model* m, int32_t out[6]) {
     if (!m || !out) return SIMINF_E_ARG;
     if (m->groups.empty()) {
-        for (int i = 0; i < 5; ++i) out[i] = 0;
+        for (int i = 0; i < 6; ++i) out[i] = 0;
         return SIMINF_OK;
     }
     const Group& g = m->groups[0];
     out[0] = g.block;
     out[1] = g.blocks;
     out[2] = g.mode;
-    out[3] = 1;
+    out[3] = g.p.pipeline;
     out[4] = m->opt.order;
+    out[5] = g.p.nbig;
+    return SIMINF_OK;
+}
+
+int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_stream, double* best_ms) {
+    if (!m || repeats < 1) return SIMINF_E_ARG;
+    if (m->groups.empty()) return SIMINF_OK;
+    finish(m);
+    struct Cand {
+        int block, wide_scale, pipeline;
+    };
+    std::vector<Cand> cands;
+    for (int block : {64, 128, 256})
+        for (int scale : {0, 1, 2, 4})  // wide nodes: none, half, the default, twice the default
+            for (int pipe : {1, 2}) cands.push_back({block, scale, pipe});
+    double best = 1e300;
+    Cand pick = cands[0];
+    bool any = false;
+    for (const Cand& c : cands) {
+        bool ok = true;
+        for (Group& g : m->groups) {
+            const int h = default_wide(m, g);
+            const int nb = c.wide_scale == 0 ? 0 : c.wide_scale == 1 ? h / 2 : c.wide_scale == 2 ? h : 2 * h;
+            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode) != SIMINF_OK) ok = false;
+        }
+        if (!ok) continue;
+        std::vector<double> t;
+        for (int r = 0; r < repeats && ok; ++r) {
+            double ms[2];
+            if (siminf_run(m, seed + (uint64_t)r, 0, hip_stream) != SIMINF_OK || finish(m) != SIMINF_OK ||
+                siminf_timing(m, ms) != SIMINF_OK)
+                ok = false;
+            else
+                t.push_back(ms[0]);
+        }
+        if (!ok) continue;
+        std::sort(t.begin(), t.end());
+        const double med = t[t.size() / 2];
+        if (med < best) {
+            best = med;
+            pick = c;
+            any = true;
+        }
+    }
+    if (!any) return SIMINF_E_DEVICE;
+    for (Group& g : m->groups) {
+        const int h = default_wide(m, g);
+        const int nb = pick.wide_scale == 0 ? 0 : pick.wide_scale == 1 ? h / 2 : pick.wide_scale == 2 ? h : 2 * h;
+        configure(m, g, pick.block, nb, pick.pipeline, m->opt.mode);
+    }
+    if (best_ms) *best_ms = best;
     return SIMINF_OK;
 }
 

@@ -1,28 +1,35 @@
 // ssa_kernels.hip -- gfx950 kernels of the split-step direct-method SSA
 // (section 2.3 and Appendix A of arXiv 1605.01421): one lane per node.
 //
-// Two persistent kernels per model:
-//  * free_kernel: used when the run has no external transfers.  Nodes are
-//    then independent for the whole run, so each wavefront takes 64-node
-//    chunks from a work queue and carries every node through all days with
-//    the state in registers; no grid-wide synchronisation at all.
-//  * sync_kernel: used when external transfers exist.  Launched
-//    cooperatively (all workgroups resident); every day all lanes run SSA +
-//    E1 for their nodes, and on days with external transfers a grid barrier
-//    is followed by workgroup 0 applying that day's transfers level by level
-//    (events of one level touch disjoint nodes), a second barrier, and the
-//    post-time step.
+// Three persistent kernels per model, chosen by the host runtime:
+//  * free_kernel (no external transfers): nodes are independent for the whole
+//    run, so each wavefront takes 64-node chunks from a work queue and carries
+//    every node through all days with its state in registers.
+//  * flow_kernel (external transfers, every node resident): node state stays
+//    in registers and transfers are applied peer to peer.  Each node walks its
+//    own transfers in key order; as the source it samples the individuals,
+//    removes them and posts the (shifted) counts to the transfer's mailbox
+//    word; as the destination it waits for that word and adds the counts.
+//    Only the per-node order matters for the result, so this equals the
+//    serial order; nodes without transfers never wait, and there is no
+//    grid-wide barrier.
+//  * sync_kernel (external transfers, more nodes than resident lanes): all
+//    lanes meet at a grid barrier on every day with transfers; workgroup 0
+//    applies them level by level in global memory; a second barrier follows.
+// The flow and sync kernels are launched cooperatively (all workgroups
+// resident).  Every wait has a spin limit that turns a stall into an error.
 #include "device_math.h"
 #include "internal.h"
 #include "models.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace siminf {
 
 namespace {
 
-constexpr int E_NEG_STATE = -5, E_BAD_RATE = -6, E_OVERDRAW = -7, E_PTS = -9, E_DEVICE = -4;
+constexpr int E_NEG_STATE = -5, E_BAD_RATE = -6, E_OVERDRAW = -7, E_PTS = -9;
 constexpr int EV_EXIT = 0, EV_ENTER = 1, EV_EXTTRANS = 3;
 constexpr unsigned SPIN_LIMIT = 1u << 22;
 // Transitions of one node within one unit of time beyond which the rates are
@@ -39,13 +46,38 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
     return x;
 }
 
-// First step index whose error stops further work (wave-uniform).
+__device__ __forceinline__ uint64_t load_error_step(Ctrl* c) {
+    return __hip_atomic_load(&c->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 44;
+}
+
+// First step whose error stops further work, read by lane 0 (wave-uniform).
 __device__ __forceinline__ uint64_t error_step(Ctrl* c) {
     uint64_t k = 0;
-    if ((threadIdx.x & (WAVE - 1)) == 0)
-        k = __hip_atomic_load(&c->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    k = __shfl(k, 0, WAVE);
-    return k >> 44;
+    if ((threadIdx.x & (WAVE - 1)) == 0) k = load_error_step(c);
+    return __shfl(k, 0, WAVE);
+}
+
+// Waits until *flag >= target.  Polls with relaxed loads (no cache
+// maintenance per poll), checks for an abort or an earlier step's error every
+// 256 polls, and issues one acquire fence once the target is reached.  After
+// SPIN_LIMIT polls it sets abort so that every other wait ends too.  Returns
+// true if the target was reached.
+__device__ __forceinline__ bool wait_at_least(unsigned int* flag, unsigned target, Ctrl* c, int step,
+                                              bool fence = true) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if ((++spins & 255u) == 0) {
+            if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+            if (load_error_step(c) < (uint64_t)step) return false;
+            if (spins > SPIN_LIMIT) {
+                __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if (fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
 }
 
 template <class M>
@@ -56,106 +88,196 @@ struct Node {
     double gd[M::NGD];
 };
 
+__device__ __forceinline__ bool rate_ok(double w) { return w >= 0.0 && isfinite(w); }
+
+struct StepRandoms {
+    double e;   // -log(r1): the Exp(1) variate of the waiting time
+    double r2;  // uniform for the inversion search
+};
+
+__device__ __forceinline__ StepRandoms step_randoms(uint32_t k0, uint32_t k1, uint32_t step, uint32_t day,
+                                                    uint32_t node, uint32_t tag) {
+    const Block4 r = philox10(k0, k1, step, day, node, tag);
+    return {-series_log(open_uniform(r.x, r.y)), open_uniform(r.z, r.w)};
+}
+
 template <class M>
-__device__ __forceinline__ bool rate_ok(double w) {
-    return w >= 0.0 && isfinite(w);
+struct Transition {
+    int32_t u[M::NC];
+    double w0, w1;
+    int err;
+};
+
+// Inversion (first transition with positive rate whose cumulative sum
+// reaches x = lambda*r2; the running sum after the first rate is w0), the
+// state after adding column n of S, and the rates the dependency graph marks
+// for recomputation.  err: E_NEG_STATE if a compartment went negative, else
+// E_BAD_RATE if a recomputed rate is negative or not finite, else 0.
+template <class M>
+__device__ __forceinline__ Transition<M> transition(const KParams& p, const Node<M>& s, double w0, double w1,
+                                                    double x) {
+    Transition<M> r;
+    const int n = (w0 > 0.0 && x <= w0) ? 0 : (w1 > 0.0 ? 1 : 0);
+    bool neg = false;
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c) {
+        r.u[c] = s.u[c] + (n ? p.S[c + M::NC] : p.S[c]);
+        neg |= r.u[c] < 0;
+    }
+    const uint32_t g = n ? p.Gmask[1] : p.Gmask[0];
+    r.w0 = (g & 1u) ? M::template rate<0>(r.u, s.v, s.ld, s.gd) : w0;
+    r.w1 = (g & 2u) ? M::template rate<1>(r.u, s.v, s.ld, s.gd) : w1;
+    r.err = neg ? E_NEG_STATE : (rate_ok(r.w0) && rate_ok(r.w1)) ? 0 : E_BAD_RATE;
+    return r;
 }
 
 // Direct-method SSA of one node from time t to the day boundary T
-// (Appendix A, lines 8-19).  Returns 0 or an error code.
-template <class M>
+// (Appendix A, lines 8-19): lambda = w0 + w1, tau = -log(r1)/lambda, stop if
+// t + tau >= T, else pick the transition by inversion with r2, apply its
+// column of S and recompute the rates marked in G.  With PIPE the random
+// numbers of the next step (which do not depend on the state) are computed
+// while the current step's dependent chain runs; the values are identical.
+template <class M, bool PIPE>
 __device__ __forceinline__ int ssa_to_boundary(const KParams& p, Node<M>& s, double t, double T,
                                                uint32_t day_word, uint32_t node, uint32_t stream,
-                                               unsigned long long& transitions,
-                                               unsigned long long& draws) {
+                                               unsigned long long& transitions, unsigned long long& draws) {
     static_assert(M::NT == 2, "kernels are written for two-transition models");
     double w0 = M::template rate<0>(s.u, s.v, s.ld, s.gd);
     double w1 = M::template rate<1>(s.u, s.v, s.ld, s.gd);
-    if (!rate_ok<M>(w0) || !rate_ok<M>(w1)) return E_BAD_RATE;
+    if (!rate_ok(w0) || !rate_ok(w1)) return E_BAD_RATE;
     const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
     const uint32_t tag = stream & 0xFFFFFFu;
-    for (uint32_t step = 0;; ++step) {
-        double lam = 0.0;
+    double lam = 0.0;
+    lam = lam + w0;
+    lam = lam + w1;
+    if (!(lam > 0.0)) return 0;
+    StepRandoms cur = step_randoms(k0, k1, 0u, day_word, node, tag);
+    for (uint32_t step = 0;;) {
+        if (step == STEP_LIMIT) return E_BAD_RATE;
+        draws += 1;
+        StepRandoms nxt{0.0, 0.0};
+        if constexpr (PIPE) nxt = step_randoms(k0, k1, step + 1u, day_word, node, tag);
+        const double tau = cur.e / lam;
+        const double tn = t + tau;
+        // the transition, its state and the recomputed rates do not depend on
+        // tau: they are computed alongside the division and kept only if the
+        // step stays inside the day
+        const Transition<M> nx = transition<M>(p, s, w0, w1, lam * cur.r2);
+        if (tn >= T) break;
+        t = tn;
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) s.u[c] = nx.u[c];
+        w0 = nx.w0;
+        w1 = nx.w1;
+        transitions += 1;
+        if (nx.err) return nx.err;
+        lam = 0.0;
         lam = lam + w0;
         lam = lam + w1;
         if (!(lam > 0.0)) break;
-        if (step == STEP_LIMIT) return E_BAD_RATE;
-        draws += 1;
-        const Block4 r = philox10(k0, k1, step, day_word, node, tag);
-        const double r1 = open_uniform(r.x, r.y);
-        const double r2 = open_uniform(r.z, r.w);
-        const double tau = (-series_log(r1)) / lam;
-        const double tn = t + tau;
-        if (tn >= T) break;
-        t = tn;
-        // inversion: first transition with positive rate whose cumulative
-        // sum reaches lam*r2; the running sum after the first rate is w0.
-        const double x = lam * r2;
-        const int n = (w0 > 0.0 && x <= w0) ? 0 : (w1 > 0.0 ? 1 : 0);
-        bool neg = false;
-#pragma unroll
-        for (int c = 0; c < M::NC; ++c) {
-            s.u[c] += n ? p.S[c + M::NC] : p.S[c];
-            neg |= s.u[c] < 0;
-        }
-        transitions += 1;
-        if (neg) return E_NEG_STATE;
-        const uint32_t g = n ? p.Gmask[1] : p.Gmask[0];
-        if (g & 1u) w0 = M::template rate<0>(s.u, s.v, s.ld, s.gd);
-        if (g & 2u) w1 = M::template rate<1>(s.u, s.v, s.ld, s.gd);
-        if (!rate_ok<M>(w0) || !rate_ok<M>(w1)) return E_BAD_RATE;
+        ++step;
+        if constexpr (PIPE)
+            cur = nxt;
+        else
+            cur = step_randoms(k0, k1, step, day_word, node, tag);
     }
     return 0;
 }
 
-// One scheduled event (section 3.3) on node state u (and destination ud for
-// an external transfer).  Indices were validated when the model was created.
-// Returns 0 or E_OVERDRAW; on error the states are unchanged.
+__device__ __forceinline__ double read_lane(double x, int lane) {
+    const long long bits = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)bits, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The same SSA for one node carried by a whole wavefront: every lane holds
+// the node's state and runs the same dependent chain (so the state stays
+// wave-uniform), while the random numbers, which do not depend on the state,
+// are drawn 64 steps at a time with lane j computing step base + j.  Only
+// lane 0 counts.  Bit-identical to ssa_to_boundary.
+template <class M>
+__device__ __forceinline__ int ssa_wide(const KParams& p, Node<M>& s, double t, double T, uint32_t day_word,
+                                        uint32_t node, uint32_t stream, unsigned long long& transitions,
+                                        unsigned long long& draws) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    double w0 = M::template rate<0>(s.u, s.v, s.ld, s.gd);
+    double w1 = M::template rate<1>(s.u, s.v, s.ld, s.gd);
+    if (!rate_ok(w0) || !rate_ok(w1)) return E_BAD_RATE;
+    const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
+    const uint32_t tag = stream & 0xFFFFFFu;
+    double lam = 0.0;
+    lam = lam + w0;
+    lam = lam + w1;
+    if (!(lam > 0.0)) return 0;
+    const unsigned long long one = lane == 0 ? 1ull : 0ull;
+    for (uint32_t base = 0;; base += WAVE) {
+        if (base >= STEP_LIMIT) return E_BAD_RATE;
+        const StepRandoms mine = step_randoms(k0, k1, base + (uint32_t)lane, day_word, node, tag);
+        for (int i = 0; i < WAVE; ++i) {
+            const double e = read_lane(mine.e, i);
+            const double r2 = read_lane(mine.r2, i);
+            draws += one;
+            const double tau = e / lam;
+            const double tn = t + tau;
+            const Transition<M> nx = transition<M>(p, s, w0, w1, lam * r2);
+            if (tn >= T) return 0;
+            t = tn;
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) s.u[c] = nx.u[c];
+            w0 = nx.w0;
+            w1 = nx.w1;
+            transitions += one;
+            if (nx.err) return nx.err;
+            lam = 0.0;
+            lam = lam + w0;
+            lam = lam + w1;
+            if (!(lam > 0.0)) return 0;
+        }
+    }
+}
+
+// One scheduled event (section 3.3) from its packed record, on node state u
+// (and destination ud for an external transfer).  Indices were validated
+// when the model was created.  Returns 0 or E_OVERDRAW (state unchanged).
 template <int NC>
-__device__ __forceinline__ int apply_event(const KParams& p, const EventSoA& ev, int e, int32_t (&u)[NC],
-                                        int32_t (&ud)[NC], uint32_t stream) {
-    const int type = ev.type[e];
-    const uint32_t mask = p.Emask[ev.select[e]];
+__device__ __forceinline__ int apply_event(const int4 rec, const double* prop, int e, uint64_t seed,
+                                           uint32_t stream, int32_t (&u)[NC], int32_t (&ud)[NC]) {
+    const uint32_t w = (uint32_t)rec.y;
+    const int type = (int)(w & 3u);
+    const uint32_t mask = (w >> 2) & 0xFu;
+    // every per-compartment update below is an unconditional select so that
+    // the state stays in registers (no computed addresses)
     if (type == EV_ENTER) {
         // all n individuals go to the first selected compartment
-        bool done = false;
+        const int first = __builtin_ctz(mask);
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (!done && ((mask >> c) & 1u)) {
-                u[c] += ev.n[e];
-                done = true;
-            }
+        for (int c = 0; c < NC; ++c) u[c] += (c == first) ? rec.z : 0;
         return 0;
     }
-    const int q = ev.shift[e];
-    int tgt[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) tgt[c] = q >= 0 ? c + p.Nshift[q * MAX_NC + c] : c;
     int64_t total = 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if ((mask >> c) & 1u) total += u[c];
-    int64_t n = ev.n[e];
-    if (n == 0) n = (int64_t)floor(ev.prop[e] * (double)total + 0.5);
+    for (int c = 0; c < NC; ++c) total += ((mask >> c) & 1u) ? (int64_t)u[c] : 0;
+    int64_t n = rec.z;
+    if (n == 0) n = (int64_t)floor(prop[e] * (double)total + 0.5);
     if (n > total) return E_OVERDRAW;
     int32_t take[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) take[c] = (n == total && ((mask >> c) & 1u)) ? u[c] : 0;
     if (n < total) {
-        EventWords words(p.seed, stream, (uint32_t)ev.id[e]);
+        // one individual at a time, uniformly over those not yet drawn
+        EventWords words(seed, stream, (uint32_t)rec.w);
         for (int64_t k = 0; k < n; ++k) {
             const int64_t j = words.below((uint32_t)(total - k));
             int64_t below = 0;
             bool hit = false;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                if ((mask >> c) & 1u) {
-                    below += u[c] - take[c];
-                    if (!hit && j < below) {
-                        take[c] += 1;
-                        hit = true;
-                    }
-                }
+                const bool sel = (mask >> c) & 1u;
+                below += sel ? (int64_t)(u[c] - take[c]) : 0;
+                const bool here = sel && !hit && j < below;
+                take[c] += here ? 1 : 0;
+                hit = hit || here;
             }
         }
     }
@@ -164,15 +286,15 @@ __device__ __forceinline__ int apply_event(const KParams& p, const EventSoA& ev,
     if (type == EV_EXIT) return 0;
     const bool ext = type == EV_EXTTRANS;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c) {
+        const int tgt = (int)((w >> (6 + 2 * c)) & 3u);
 #pragma unroll
-        for (int d = 0; d < NC; ++d)
-            if (tgt[c] == d) {
-                if (ext)
-                    ud[d] += take[c];
-                else
-                    u[d] += take[c];
-            }
+        for (int d = 0; d < NC; ++d) {
+            const int32_t add = (tgt == d) ? take[c] : 0;
+            ud[d] += ext ? add : 0;
+            u[d] += ext ? 0 : add;
+        }
+    }
     return 0;
 }
 
@@ -186,8 +308,8 @@ __device__ __forceinline__ void load_static(const KParams& p, Node<M>& s, int k,
     for (int l = 0; l < M::NLD; ++l) s.ld[l] = p.ld[(size_t)l * p.n + k];
 }
 
-// Writes the records of tspan indices [m0, m1) (all lanes of the wave call
-// this together; inactive lanes contribute nothing).
+// Writes the records of tspan indices [m0, m1).  All lanes of the wave call
+// this together; inactive lanes contribute nothing.
 template <class M>
 __device__ __forceinline__ void record(const KParams& p, const Node<M>& s, int k, int run, bool active,
                                        int m0, int m1) {
@@ -209,13 +331,12 @@ __device__ __forceinline__ void record(const KParams& p, const Node<M>& s, int k
 #pragma unroll
             for (int c = 0; c < M::NC; ++c) {
                 const unsigned long long val = active ? (unsigned long long)(int64_t)s.u[c] : 0ull;
-                unsigned long long* dst = p.sums + ((size_t)run * p.ntspan + m) * p.sums_nc + c;
                 if (same) {
                     const unsigned long long tot = wave_sum(val);
                     if (lane == leader)
                         atomicAdd(p.sums + ((size_t)run0 * p.ntspan + m) * p.sums_nc + c, tot);
                 } else if (active) {
-                    atomicAdd(dst, val);
+                    atomicAdd(p.sums + ((size_t)run * p.ntspan + m) * p.sums_nc + c, val);
                 }
             }
         }
@@ -236,77 +357,251 @@ __device__ __forceinline__ void add_counters(Ctrl* c, unsigned long long tr, uns
     }
 }
 
+struct Tally {
+    unsigned long long tr = 0, nd = 0, ev = 0, dr = 0;
+};
+
+// Loads node k's constant data and initial state (registers for the run).
+template <class M>
+__device__ __forceinline__ void load_node(const KParams& p, int k, Node<M>& s, int& run, uint32_t& node,
+                                          uint32_t& stream, int64_t& ord, int& cur, int& cend, int4& nrec) {
+    load_static<M>(p, s, k, run);
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c) s.u[c] = p.u0[(size_t)c * p.n + k];
+#pragma unroll
+    for (int c = 0; c < M::NV; ++c) s.v[c] = p.v0[(size_t)c * p.n + k];
+    node = (uint32_t)p.node_idx[k];
+    stream = p.stream_base + (uint32_t)run;
+    ord = p.node_ord[k];
+    cur = p.e1_off[k];
+    cend = p.e1_off[k + 1];
+    if (cur < cend) nrec = p.e1.rec[cur];
+}
+
+// SSA to day boundary b, then the node's E1 events with time <= T.  With
+// wide, the whole wavefront carries the node (ssa_wide); event tallies are
+// then kept by lane 0 only.  nrec holds the record at cur (loaded ahead so
+// that days without events wait for no memory access).
+template <class M, bool PIPE>
+__device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, int64_t day, uint32_t node,
+                                           uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec,
+                                           bool& dead, Tally& t, bool wide) {
+    const double T = (double)day;
+    const double t0 = b == 0 ? p.t0 : T - 1.0;
+    int rc = wide ? ssa_wide<M>(p, s, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr)
+                  : ssa_to_boundary<M, PIPE>(p, s, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr);
+    if (rc) {
+        raise_error(p.ctrl, b, PH_SSA, ord, rc);
+        dead = true;
+        return;
+    }
+    while (cur < cend && (double)nrec.x <= T) {
+        rc = apply_event<M::NC>(nrec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
+        if (rc) {
+            raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
+            dead = true;
+            return;
+        }
+        t.ev += (!wide || (threadIdx.x & (WAVE - 1)) == 0) ? 1 : 0;
+        ++cur;
+        if (cur < cend) nrec = p.e1.rec[cur];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // free-running kernel (no external transfers)
 // ---------------------------------------------------------------------------
-template <class M>
+template <class M, bool PIPE>
 __global__ void __launch_bounds__(256) free_kernel(KParams p) {
     const int lane = threadIdx.x & (WAVE - 1);
-    unsigned long long n_tr = 0, n_nd = 0, n_ev = 0, n_dr = 0;
+    Tally t;
     for (;;) {
         unsigned chunk = 0;
         if (lane == 0) chunk = atomicAdd(&p.ctrl->work[p.group], 1u);
         chunk = __shfl(chunk, 0, WAVE);
         if (chunk >= (unsigned)p.nchunks) break;
-        const int k = (int)chunk * WAVE + lane;
+        // chunks [0, nbig): one heavy node per wavefront; then 64 nodes per chunk
+        const bool wide = (int)chunk < p.nbig;
+        const int k = wide ? (int)chunk : p.nbig + ((int)chunk - p.nbig) * WAVE + lane;
         const bool active = k < p.n;
+        const bool owner = active && (!wide || lane == 0);  // writes records
         Node<M> s;
         int run = 0, cur = 0, cend = 0;
         uint32_t node = 0, stream = 0;
         int64_t ord = 0;
-        if (active) {
-            load_static<M>(p, s, k, run);
-#pragma unroll
-            for (int c = 0; c < M::NC; ++c) s.u[c] = p.u0[(size_t)c * p.n + k];
-#pragma unroll
-            for (int c = 0; c < M::NV; ++c) s.v[c] = p.v0[(size_t)c * p.n + k];
-            node = (uint32_t)p.node_idx[k];
-            stream = p.stream_base + (uint32_t)run;
-            ord = p.node_ord[k];
-            cur = p.e1_off[k];
-            cend = p.e1_off[k + 1];
-        }
+        int4 nrec = make_int4(0, 0, 0, 0);
+        if (active) load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec);
         bool dead = false;
+        uint64_t key_raw = 0;  // error key, refreshed every 8 days and read 8 days later
         for (int b = 0; b < p.nb; ++b) {
-            if (error_step(p.ctrl) < (uint64_t)b) break;
-            const int64_t day = p.T1 + b;
-            const double T = (double)day;
-            const double t = b == 0 ? p.t0 : T - 1.0;
-            if (active && !dead) {
-                int rc = ssa_to_boundary<M>(p, s, t, T, (uint32_t)(int32_t)day, node, stream, n_tr, n_dr);
-                if (rc) {
-                    raise_error(p.ctrl, b, PH_SSA, ord, rc);
-                    dead = true;
-                }
-                while (!dead && cur < cend && (double)p.e1.time[cur] <= T) {
-                    rc = apply_event<M::NC>(p, p.e1, cur, s.u, s.u, stream);
-                    if (rc) {
-                        raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
-                        dead = true;
-                    } else {
-                        ++n_ev;
-                        ++cur;
-                    }
-                }
-                if (!dead && !M::pts(s.v, s.u, s.ld, s.gd, day)) {
-                    raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
-                    dead = true;
-                }
-                ++n_nd;
+            if ((b & 7) == 0) {
+                if (b > 0 && (__shfl(key_raw, 0, WAVE) >> 44) < (uint64_t)b) break;
+                if (lane == 0)
+                    key_raw = __hip_atomic_load(&p.ctrl->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            record<M>(p, s, k, run, active, p.rec_off[b], p.rec_off[b + 1]);
+            const int64_t day = p.T1 + b;
+            if (active && !dead) {
+                ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
+                if (!dead && !M::pts(s.v, s.u, s.ld, s.gd, day)) {
+                    if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
+                    dead = true;
+                }
+                t.nd += owner ? 1 : 0;
+            }
+            record<M>(p, s, k, run, owner, p.rec_off[b], p.rec_off[b + 1]);
         }
     }
-    add_counters(p.ctrl, n_tr, n_nd, n_ev, n_dr);
+    add_counters(p.ctrl, t.tr, t.nd, t.ev, t.dr);
 }
 
 // ---------------------------------------------------------------------------
-// day-synchronous kernel (external transfers present); cooperative launch
+// dataflow kernel (external transfers, every node resident)
+// ---------------------------------------------------------------------------
+constexpr unsigned long long MAIL_PACKED = 1ull << 63;  // counts packed in bits 0..47
+constexpr unsigned long long MAIL_SIDE = 1ull << 62;    // counts in mail_big (release/acquire)
+
+// Posts the counts a transfer delivers: up to three 16-bit counts in one
+// atomic word, else through the side array.
+template <int NC>
+__device__ __forceinline__ void post_mail(const KParams& p, int e, const int32_t (&cnt)[NC]) {
+    bool small = true;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) small = small && cnt[c] <= 0xFFFF;
+    if (small && NC <= 3) {
+        unsigned long long w = MAIL_PACKED;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w |= (unsigned long long)cnt[c] << (16 * c);
+        __hip_atomic_store(&p.mail[e], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) p.mail_big[(size_t)e * MAX_NC + c] = cnt[c];
+        __hip_atomic_store(&p.mail[e], MAIL_SIDE, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Adds the counts of a posted mailbox word w to u.
+template <int NC>
+__device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long long w, int32_t (&u)[NC]) {
+    if (w & MAIL_PACKED) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u[c] += (int32_t)((w >> (16 * c)) & 0xFFFFull);
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u[c] += p.mail_big[(size_t)e * MAX_NC + c];
+    }
+}
+
+template <class M, bool PIPE>
+__global__ void __launch_bounds__(256) flow_kernel(KParams p) {
+    Tally t;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int gw = blockIdx.x * (blockDim.x / WAVE) + (int)(threadIdx.x / WAVE);
+    // waves [0, nbig): one heavy node per wavefront; then 64 nodes per wave
+    const bool wide = gw < p.nbig;
+    const int k = wide ? gw : p.nbig + (gw - p.nbig) * WAVE + lane;
+    const bool active = k < p.n;
+    const bool owner = active && (!wide || lane == 0);
+    Node<M> s;
+    int run = 0, cur = 0, cend = 0, tcur = 0, tend = 0;
+    uint32_t node = 0, stream = 0;
+    int64_t ord = 0;
+    int4 nrec = make_int4(0, 0, 0, 0), item = make_int4(0, INT_MAX, 0, 0), trec = make_int4(0, 0, 0, 0);
+    if (active) {
+        load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec);
+        tcur = p.e2n_off[k];
+        tend = p.e2n_off[k + 1];
+        if (tcur < tend) {
+            item = p.e2n_item[tcur];
+            trec = p.e2n_rec[tcur];
+        }
+    }
+    bool dead = false;
+    uint64_t key_raw = 0;  // error key, refreshed every 8 days and read 8 days later
+    for (int b = 0; b < p.nb; ++b) {
+        if ((b & 7) == 0) {
+            if (b > 0 && (__shfl(key_raw, 0, WAVE) >> 44) < (uint64_t)b) break;
+            if (lane == 0)
+                key_raw = __hip_atomic_load(&p.ctrl->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const int64_t day = p.T1 + b;
+        if (active && !dead) ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
+
+        // this step's external transfers of the node, in key order.  The loop
+        // is uniform over the wavefront and every lane that can move on does:
+        // sources never wait, so no lane can block another one of its wave.
+        bool pending = active && item.y == b;
+        unsigned spins = 0;
+        while (__any(pending)) {
+            bool moved = false;
+            if (pending) {
+                const int e = item.x;
+                if (item.z != 1) {
+                    // source (or source and destination): sample and post
+                    int32_t got[M::NC];
+#pragma unroll
+                    for (int c = 0; c < M::NC; ++c) got[c] = 0;
+                    const uint32_t ev_stream = p.stream_base + (uint32_t)item.w;
+                    int rc = dead ? 0 : apply_event<M::NC>(trec, p.e2.prop, e, p.seed, ev_stream, s.u, got);
+                    if (rc) {
+                        if (owner) raise_error(p.ctrl, b, PH_E2, p.e2.ordinal[e], rc);
+                        dead = true;
+                    }
+                    if (item.z == 2) {
+#pragma unroll
+                        for (int c = 0; c < M::NC; ++c) s.u[c] += got[c];
+                    } else if (owner) {
+                        post_mail<M::NC>(p, e, got);
+                    }
+                    t.ev += (owner && !rc && !dead) ? 1 : 0;
+                    moved = true;
+                } else {
+                    const unsigned long long w =
+                        __hip_atomic_load(&p.mail[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (w) {
+                        take_mail<M::NC>(p, e, w, s.u);
+                        moved = true;
+                    }
+                }
+                if (moved) {
+                    ++tcur;
+                    if (tcur < tend) {
+                        item = p.e2n_item[tcur];
+                        trec = p.e2n_rec[tcur];
+                    } else {
+                        item.y = INT_MAX;
+                    }
+                }
+                pending = item.y == b;
+            }
+            if (!__any(moved)) {
+                if ((++spins & 255u) == 0) {
+                    const bool quit = __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                                      load_error_step(p.ctrl) < (uint64_t)b;
+                    if (spins > SPIN_LIMIT && lane == 0)
+                        __hip_atomic_store(&p.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (__any(quit) || spins > SPIN_LIMIT) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        if (active && !dead) {
+            if (!M::pts(s.v, s.u, s.ld, s.gd, day)) {
+                if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
+                dead = true;
+            }
+            t.nd += owner ? 1 : 0;
+        }
+        record<M>(p, s, k, run, owner, p.rec_off[b], p.rec_off[b + 1]);
+    }
+    add_counters(p.ctrl, t.tr, t.nd, t.ev, t.dr);
+}
+
+// ---------------------------------------------------------------------------
+// barrier kernel (external transfers, several nodes per lane)
 // ---------------------------------------------------------------------------
 // Grid barrier on a monotone arrival counter: the epoch-th barrier completes
-// when epoch * gridDim.x workgroups have arrived.  A wait that exceeds the
-// spin limit sets `abort`, after which every barrier returns at once (the run
-// then reports SIMINF_E_DEVICE) so the kernel always terminates.
+// when epoch * gridDim.x workgroups have arrived.
 __device__ __forceinline__ void grid_barrier(Ctrl* c, unsigned epoch) {
     __threadfence();
     __syncthreads();
@@ -314,14 +609,15 @@ __device__ __forceinline__ void grid_barrier(Ctrl* c, unsigned epoch) {
         const unsigned target = epoch * gridDim.x;
         __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(&c->bar_count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(&c->bar_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             if (++spins > SPIN_LIMIT) {
                 __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
-            __builtin_amdgcn_s_sleep(4);
+            __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     __threadfence();
@@ -335,19 +631,17 @@ __device__ __forceinline__ void load_live(const KParams& p, Node<M>& s, int k) {
     for (int c = 0; c < M::NV; ++c) s.v[c] = p.v[(size_t)c * p.n + k];
 }
 
-template <class M>
+template <class M, bool PIPE>
 __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nthreads = gridDim.x * blockDim.x;
     const int wave_base = gtid - lane;
-    unsigned long long n_tr = 0, n_nd = 0, n_ev = 0, n_dr = 0;
+    Tally t;
     unsigned epoch = 0;
     for (int b = 0; b < p.nb; ++b) {
         const bool stop = error_step(p.ctrl) < (uint64_t)b;
         const int64_t day = p.T1 + b;
-        const double T = (double)day;
-        const double t = b == 0 ? p.t0 : T - 1.0;
         const bool e2day = p.e2_step[b + 1] > p.e2_step[b];
         for (int base = wave_base; base < p.n; base += nthreads) {
             const int k = base + lane;
@@ -360,24 +654,11 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
                 const uint32_t stream = p.stream_base + (uint32_t)run;
                 const int64_t ord = p.node_ord[k];
                 bool dead = false;
-                int rc = ssa_to_boundary<M>(p, s, t, T, (uint32_t)(int32_t)day, (uint32_t)p.node_idx[k],
-                                            stream, n_tr, n_dr);
-                if (rc) {
-                    raise_error(p.ctrl, b, PH_SSA, ord, rc);
-                    dead = true;
-                }
                 int cur = p.e1_cur[k];
                 const int cend = p.e1_off[k + 1];
-                while (!dead && cur < cend && (double)p.e1.time[cur] <= T) {
-                    rc = apply_event<M::NC>(p, p.e1, cur, s.u, s.u, stream);
-                    if (rc) {
-                        raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
-                        dead = true;
-                    } else {
-                        ++n_ev;
-                        ++cur;
-                    }
-                }
+                int4 nrec = cur < cend ? p.e1.rec[cur] : make_int4(0, 0, 0, 0);
+                ssa_and_e1<M, PIPE>(p, s, b, day, (uint32_t)p.node_idx[k], stream, ord, cur, cend, nrec, dead, t,
+                                    false);
                 p.e1_cur[k] = cur;
                 if (!e2day && !dead && !M::pts(s.v, s.u, s.ld, s.gd, day))
                     raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
@@ -387,7 +668,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
 #pragma unroll
                     for (int c = 0; c < M::NV; ++c) p.v[(size_t)c * p.n + k] = s.v[c];
                 }
-                ++n_nd;
+                ++t.nd;
             }
             if (!e2day) record<M>(p, s, k, run, active, p.rec_off[b], p.rec_off[b + 1]);
         }
@@ -395,8 +676,8 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
 
         grid_barrier(p.ctrl, ++epoch);
         if (blockIdx.x == 0) {
-            // external transfers of this step, level by level, in key order;
-            // the branch and the level loop are uniform over workgroup 0
+            // this step's transfers, level by level in key order; the branch
+            // and the level loop are uniform over workgroup 0
             for (int L = p.e2_step[b]; L < p.e2_step[b + 1]; ++L) {
                 for (int e = p.e2_lvl[L] + (int)threadIdx.x; e < p.e2_lvl[L + 1]; e += blockDim.x) {
                     const int src = p.e2.node[e], dst = p.e2.dest[e];
@@ -407,13 +688,12 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
                         ud[c] = p.u[(size_t)c * p.n + dst];
                         before[c] = ud[c];
                     }
-                    const uint32_t stream = p.stream_base + (uint32_t)p.node_run[src];
-                    const int rc = apply_event<M::NC>(p, p.e2, e, us, ud, stream);
+                    const uint32_t stream = p.stream_base + (uint32_t)p.e2.run[e];
+                    const int rc = apply_event<M::NC>(p.e2.rec[e], p.e2.prop, e, p.seed, stream, us, ud);
                     if (rc) {
                         raise_error(p.ctrl, b, PH_E2, p.e2.ordinal[e], rc);
                     } else {
                         if (dst == src) {
-                            // one node: removal and (shifted) re-addition both apply
 #pragma unroll
                             for (int c = 0; c < M::NC; ++c)
                                 p.u[(size_t)c * p.n + src] = us[c] + (ud[c] - before[c]);
@@ -424,7 +704,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
                                 p.u[(size_t)c * p.n + dst] = ud[c];
                             }
                         }
-                        ++n_ev;
+                        ++t.ev;
                     }
                 }
                 __threadfence_block();
@@ -441,17 +721,14 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
             if (active) {
                 load_static<M>(p, s, k, run);
                 load_live<M>(p, s, k);
-                if (!M::pts(s.v, s.u, s.ld, s.gd, day))
-                    raise_error(p.ctrl, b, PH_PTS, p.node_ord[k], E_PTS);
+                if (!M::pts(s.v, s.u, s.ld, s.gd, day)) raise_error(p.ctrl, b, PH_PTS, p.node_ord[k], E_PTS);
 #pragma unroll
                 for (int c = 0; c < M::NV; ++c) p.v[(size_t)c * p.n + k] = s.v[c];
             }
             record<M>(p, s, k, run, active, p.rec_off[b], p.rec_off[b + 1]);
         }
     }
-    add_counters(p.ctrl, n_tr, n_nd, n_ev, n_dr);
-    if (gtid == 0 && __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        raise_error(p.ctrl, 0, 0, 0, E_DEVICE);
+    add_counters(p.ctrl, t.tr, t.nd, t.ev, t.dr);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,11 +744,14 @@ __global__ void init_kernel(KParams p, int nc, int nv, int first_rec, int reset_
         for (int i = 0; i < MAX_GROUPS; ++i) p.ctrl->work[i] = 0;
         p.ctrl->bar_count = 0;
         p.ctrl->abort = 0;
+        p.ctrl->e2done = 0;
     }
     if (reset_ctrl && sums_init)
         for (long long i = gtid; i < sums_len; i += nthreads) p.sums[i] = sums_init[i];
+    if (p.mode == MODE_FLOW)
+        for (int e = gtid; e < p.n_e2; e += nthreads) p.mail[e] = 0ull;
     for (int k = gtid; k < p.n; k += nthreads) {
-        if (p.mode == 1) {
+        if (p.mode == MODE_BARRIER) {
             for (int c = 0; c < nc; ++c) p.u[(size_t)c * p.n + k] = p.u0[(size_t)c * p.n + k];
             for (int c = 0; c < nv; ++c) p.v[(size_t)c * p.n + k] = p.v0[(size_t)c * p.n + k];
             p.e1_cur[k] = p.e1_off[k];
@@ -495,19 +775,16 @@ __global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv,
         const int m = (int)(idx / nn), i = (int)(idx % nn);
         const int k = pos[i];
         if (Uo)
-            for (int c = 0; c < nc; ++c)
-                Uo[((size_t)m * nn + i) * nc + c] = U[((size_t)m * nc + c) * n + k];
+            for (int c = 0; c < nc; ++c) Uo[((size_t)m * nn + i) * nc + c] = U[((size_t)m * nc + c) * n + k];
         if (Vo)
-            for (int c = 0; c < nv; ++c)
-                Vo[((size_t)m * nn + i) * nv + c] = V[((size_t)m * nv + c) * n + k];
+            for (int c = 0; c < nv; ++c) Vo[((size_t)m * nn + i) * nv + c] = V[((size_t)m * nv + c) * n + k];
     }
 }
 
 // One workgroup per (set, tspan index): prevalence of every replicate, rank
 // sort (ties by replicate index), type-7 quantiles.
-__global__ void prevalence_kernel(const unsigned long long* sums, int ntspan, int nc, int case_c,
-                                  uint32_t mask, int reps, int k0, int nk, const double* probs, int nq,
-                                  float* out) {
+__global__ void prevalence_kernel(const unsigned long long* sums, int ntspan, int nc, int case_c, uint32_t mask,
+                                  int reps, int k0, int nk, const double* probs, int nq, float* out) {
     extern __shared__ double sh[];
     double* val = sh;
     double* sorted = sh + reps;
@@ -540,77 +817,70 @@ __global__ void prevalence_kernel(const unsigned long long* sums, int ntspan, in
     }
 }
 
-template <class M>
-hipError_t launch_model(const KParams& p, int block, int blocks, bool cooperative, hipStream_t st) {
-    if (cooperative) {
-        KParams arg = p;
-        void* args[] = {&arg};
-        return hipLaunchCooperativeKernel((const void*)sync_kernel<M>, dim3(blocks), dim3(block), args, 0, st);
-    }
-    free_kernel<M><<<blocks, block, 0, st>>>(p);
-    return hipGetLastError();
+template <class M, bool PIPE>
+const void* kernel_for(int mode) {
+    if (mode == MODE_FLOW) return (const void*)flow_kernel<M, PIPE>;
+    if (mode == MODE_BARRIER) return (const void*)sync_kernel<M, PIPE>;
+    return (const void*)free_kernel<M, PIPE>;
 }
 
 template <class M>
-int occupancy(int mode, int block) {
-    int n = 0;
-    hipError_t e = mode == 1
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sync_kernel<M>, block, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, free_kernel<M>, block, 0);
-    return e == hipSuccess ? n : 0;
+const void* kernel_for(int mode, int pipeline) {
+    return pipeline ? kernel_for<M, true>(mode) : kernel_for<M, false>(mode);
+}
+
+const void* model_kernel(int model, int mode, int pipeline) {
+    switch (model) {
+        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline);
+        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline);
+        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline);
+        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline);
+        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline);
+    }
+    return nullptr;
 }
 
 }  // namespace
 
 hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st) {
-    int blocks = (int)((p.n + 255) / 256);
+    int blocks = (int)((std::max(p.n, p.n_e2) + 255) / 256);
     if (sums_init) blocks = (int)std::max<long long>(blocks, (sums_len + 255) / 256);
     blocks = std::max(1, std::min(blocks, 4096));
     init_kernel<<<blocks, 256, 0, st>>>(p, nc, nv, first_rec, reset_ctrl ? 1 : 0, sums_init, sums_len);
     return hipGetLastError();
 }
 
-hipError_t launch_group(int model, const KParams& p, int block, int blocks, bool cooperative,
-                        hipStream_t st) {
-    switch (model) {
-        case M_SIR: return launch_model<ModelSIR>(p, block, blocks, cooperative, st);
-        case M_SIS: return launch_model<ModelSIS>(p, block, blocks, cooperative, st);
-        case M_SISE: return launch_model<ModelSISe>(p, block, blocks, cooperative, st);
-        case M_BIRTH_DEATH: return launch_model<ModelBirthDeath>(p, block, blocks, cooperative, st);
-        case M_IMMIGRATION_DEATH:
-            return launch_model<ModelImmigrationDeath>(p, block, blocks, cooperative, st);
-    }
-    return hipErrorInvalidValue;
+hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st) {
+    const void* fn = model_kernel(model, p.mode, p.pipeline);
+    if (!fn) return hipErrorInvalidValue;
+    KParams arg = p;
+    void* args[] = {&arg};
+    if (p.mode == MODE_FREE) return hipLaunchKernel(fn, dim3(blocks), dim3(block), args, shmem, st);
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(block), args, (unsigned)shmem, st);
 }
 
-int max_blocks_per_cu(int model, int mode, int block) {
-    switch (model) {
-        case M_SIR: return occupancy<ModelSIR>(mode, block);
-        case M_SIS: return occupancy<ModelSIS>(mode, block);
-        case M_SISE: return occupancy<ModelSISe>(mode, block);
-        case M_BIRTH_DEATH: return occupancy<ModelBirthDeath>(mode, block);
-        case M_IMMIGRATION_DEATH: return occupancy<ModelImmigrationDeath>(mode, block);
-    }
-    return 0;
+int max_blocks_per_cu(int model, int mode, int pipeline, int block, size_t shmem) {
+    const void* fn = model_kernel(model, mode, pipeline);
+    int n = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, shmem) != hipSuccess) return 0;
+    return n;
 }
 
-hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan,
-                         const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st) {
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, const int32_t* pos,
+                         int nn, int32_t* Uo, double* Vo, hipStream_t st) {
     long long total = (long long)ntspan * nn;
     int blocks = (int)std::max<long long>(1, std::min<long long>((total + 255) / 256, 8192));
     gather_kernel<<<blocks, 256, 0, st>>>(U, V, nc, nv, n, ntspan, pos, nn, Uo, Vo);
     return hipGetLastError();
 }
 
-hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc, int case_c,
-                             uint32_t mask, int reps, int k0, int nk, const double* probs, int nq,
-                             float* out, hipStream_t st) {
+hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc, int case_c, uint32_t mask,
+                             int reps, int k0, int nk, const double* probs, int nq, float* out, hipStream_t st) {
     const int sets = runs / reps;
     if (sets <= 0 || nk <= 0) return hipSuccess;
     const size_t shmem = sizeof(double) * 2 * (size_t)reps;
-    prevalence_kernel<<<sets * nk, 64, shmem, st>>>(sums, ntspan, nc, case_c, mask, reps, k0, nk, probs,
-                                                    nq, out);
+    prevalence_kernel<<<sets * nk, 64, shmem, st>>>(sums, ntspan, nc, case_c, mask, reps, k0, nk, probs, nq, out);
     return hipGetLastError();
 }
 

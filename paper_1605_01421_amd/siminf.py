@@ -44,7 +44,7 @@ class Spec(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("record", ctypes.c_int32), ("block", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("pipeline", ctypes.c_int32), ("mode", ctypes.c_int32), ("wide", ctypes.c_int32)]
 
 
 # exported entry points: name -> (restype, argtypes)
@@ -62,6 +62,7 @@ SIGNATURES = {
     "siminf_error_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "siminf_launch_info": (ctypes.c_int, [_P, _P]),
     "siminf_timing": (ctypes.c_int, [_P, _P]),
+    "siminf_autotune": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, _P, _P]),
     "siminf_destroy": (None, [_P]),
     "siminf_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "siminf_prevalence_quantiles": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
@@ -154,11 +155,11 @@ class Model:
     synchronise."""
 
     def __init__(self, spec, record: int = RECORD_FULL, block: int = 0, order: int = 0,
-                 lanes: int = 1, max_blocks: int = 0):
+                 lanes: int = 0, max_blocks: int = 0, pipeline: int = 0, mode: int = 0, wide: int = 0):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p()
-        opt = Options(record, block, order, lanes, max_blocks)
+        opt = Options(record, block, order, lanes, max_blocks, pipeline, mode, wide)
         keep: list = []
         if isinstance(spec, (list, tuple)):
             specs = [s for s, _ in spec]
@@ -240,10 +241,19 @@ class Model:
         return dict(kernel_ms=float(out[0]), run_ms=float(out[1]))
 
     def launch_info(self) -> dict:
-        out = np.zeros(5, dtype=np.int32)
+        out = np.zeros(6, dtype=np.int32)
         self._lib.siminf_launch_info(self._h, _ptr(out))
-        return dict(block=int(out[0]), blocks=int(out[1]), mode=int(out[2]), lanes=int(out[3]),
-                    order=int(out[4]))
+        return dict(block=int(out[0]), blocks=int(out[1]), mode=int(out[2]), pipeline=int(out[3]),
+                    order=int(out[4]), wide=int(out[5]))
+
+    def autotune(self, seed: int = 1, repeats: int = 2, hip_stream=None) -> float:
+        """Pick the fastest launch shape (see siminf_autotune); returns its ms."""
+        best = ctypes.c_double()
+        rc = self._lib.siminf_autotune(self._h, ctypes.c_uint64(seed), repeats, _stream_handle(hip_stream),
+                                       ctypes.byref(best))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_autotune")
+        return best.value
 
     # -- results ---------------------------------------------------------------
     def trajectory(self, run: int = 0, device: bool = False):

@@ -67,11 +67,12 @@ def test_plain_sir_100_nodes(lib):
 def test_paper_five_node_event_example(lib, infect):
     spec = W.sir_event_example(infect)
     for stream in range(4):
-        m, ref, rc = _run_both(lib, spec, 3, stream)
-        assert rc == 0
-        _compare(m, ref, what=f"five-node stream {stream}")
-        assert m.counters()["events"] == ref["events"]
-        assert m.launch_info()["mode"] == 1
+        for mode in (1, 2):
+            m, ref, rc = _run_both(lib, spec, 3, stream, mode=mode)
+            assert rc == 0
+            _compare(m, ref, what=f"five-node stream {stream} mode {mode}")
+            assert m.counters()["events"] == ref["events"]
+            assert m.launch_info()["mode"] == mode
 
 
 @pytest.mark.parametrize("Nn,days,seed", [(257, 40, 1), (1000, 90, 7)])
@@ -84,9 +85,10 @@ def test_sir_with_events_small(lib, Nn, days, seed):
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
 
 
-def test_sise_with_events_small(lib):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_sise_with_events_small(lib, mode):
     spec = W.config2(seed=4, Nn=700, days=200)
-    m, ref, rc = _run_both(lib, spec, 9, 2)
+    m, ref, rc = _run_both(lib, spec, 9, 2, mode=mode)
     assert rc == 0 and ref["status"] == 0
     _compare(m, ref, what=spec.name)
     assert np.array_equal(m.trajectory()[1], ref["V"]), "phi expected bit-identical"
@@ -112,7 +114,11 @@ def test_other_models(lib, kind):
 
 
 @pytest.mark.parametrize("opts", [dict(block=64), dict(block=128), dict(block=256), dict(order=1),
-                                  dict(max_blocks=3), dict(block=64, max_blocks=1)])
+                                  dict(mode=1), dict(mode=1, max_blocks=3), dict(mode=1, block=64, max_blocks=1),
+                                  dict(mode=2, block=128), dict(pipeline=1), dict(pipeline=2),
+                                  dict(mode=1, pipeline=2), dict(max_blocks=1, block=64),
+                                  dict(lanes=1), dict(lanes=64, wide=1), dict(lanes=64, wide=40),
+                                  dict(lanes=64, wide=600, block=256), dict(lanes=64, wide=7, block=128, pipeline=2)])
 def test_launch_shape_does_not_change_bits(lib, opts):
     spec = W.config1(seed=11, Nn=600, days=50)
     ref = oracle_run(spec, 5, 0)
@@ -175,8 +181,9 @@ def test_prevalence_quantiles(lib):
         assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1))
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("case", ["overdraw_e1", "overdraw_e2", "negative_rate"])
-def test_first_error_matches_oracle(lib, case):
+def test_first_error_matches_oracle(lib, case, mode):
     u0 = np.array([[5, 0, 0], [5, 0, 0], [5, 0, 0]])
     beta = 0.0
     if case == "overdraw_e1":
@@ -190,7 +197,7 @@ def test_first_error_matches_oracle(lib, case):
         beta = -0.1
         rows = []
     spec = W.sir_spec(u0, [0, 1, 2, 3, 4], beta, 0.1, events=W.make_events(rows))
-    m, ref, rc = _run_both(lib, spec, 1, 0)
+    m, ref, rc = _run_both(lib, spec, 1, 0, mode=mode)
     info = m.error_info()
     assert rc == ref["status"] != 0
     assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
@@ -212,12 +219,25 @@ def test_trajectory_to_device(lib):
     assert U.is_cuda and np.array_equal(U.cpu().numpy(), ref["U"])
 
 
-def test_sir_events_full_size(lib):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_sir_events_full_size(lib, mode):
     """10,000 nodes, 365 days, the benchmark workload: whole trajectory."""
     spec = W.config1()
     _say("config1 full", spec.Nn, len(spec.events["time"]))
-    m, ref, rc = _run_both(lib, spec, 2024, 0)
+    m, ref, rc = _run_both(lib, spec, 2024, 0, mode=mode)
     assert rc == 0 and ref["status"] == 0
     _compare(m, ref, what="config1 full")
     c = m.counters()
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
+def test_autotune_keeps_bits(lib):
+    spec = W.config1(seed=13, Nn=800, days=45)
+    ref = oracle_run(spec, 77, 2)
+    m = lib.Model(spec)
+    _say("autotune")
+    best = m.autotune(seed=5, repeats=1)
+    assert best > 0
+    m.run(77, 2)
+    assert m.wait() == 0
+    _compare(m, ref, what=f"autotuned {m.launch_info()}")
