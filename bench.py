@@ -38,6 +38,38 @@ OPS_PER_STEP = 260
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources of the library (identifies a kernel build)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1605_01421_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def build_workload(name):
     from paper_1605_01421_amd import workloads as W
     if name == "sir-events":
@@ -57,7 +89,7 @@ def cpu_baseline(spec, seed, seconds, gpu_counters):
     node_days = 0
     t_total = 0.0
     parity = None
-    while t_total < seconds and runs < 50:
+    while t_total < seconds and runs < 2000:
         t0 = time.perf_counter()
         r = oracle.run(spec, seed + runs, 0, nthreads=threads)
         t_total += time.perf_counter() - t0
@@ -78,7 +110,14 @@ def main():
     ap.add_argument("--workload", default="sir-events")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--order", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per node: 0 auto, 1, 64")
+    ap.add_argument("--wide", type=int, default=0, help="with --lanes 64: wavefront-wide nodes")
+    ap.add_argument("--pipeline", type=int, default=0, help="0 auto, 1 on, 2 off")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (launch shape from heuristics)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy a 256 MiB device buffer once (known-size reference "
+                         "kernel for hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -92,8 +131,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     spec = build_workload(args.workload)
-    model = siminf.Model(spec, block=args.block, order=args.order)
+    model = siminf.Model(spec, block=args.block, order=args.order, lanes=args.lanes, wide=args.wide,
+                         pipeline=args.pipeline)
     seed0 = 20240000
+    tuned_ms = None
+    if not args.no_tune:
+        tuned_ms = model.autotune(seed=seed0 - 1000, repeats=2)
     for w in range(args.warmup):
         model.run(seed0 - 1 - w)
         assert model.wait() == 0, model.error_info()
@@ -117,6 +160,11 @@ def main():
         events += c["events"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.calibrate_copy:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     mean_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     draws_per_launch = draws / args.steps
@@ -138,13 +186,17 @@ def main():
         "config": {"workload": spec.name, "nodes": spec.Nn, "days": spec.n_days,
                    "scheduled_events": int(len(spec.events["time"])), "model": "SIR",
                    "record": "U every day", "seed": seed0, "block": info["block"], "blocks": info["blocks"],
-                   "mode": "day-synchronous" if info["mode"] == 1 else "free-running"},
+                   "kernel": ["free-running", "grid-barrier", "dataflow"][info["mode"]],
+                   "wide_nodes": info["wide"], "pipeline": info["pipeline"]},
         "transitions_per_s": transitions / wall,
         "events_per_step": events / args.steps,
         "kernel_ms_mean": mean_kernel_s * 1e3,
+        "autotune_best_ms": tuned_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "sync_kernel<ModelSIR>" if info["mode"] == 1 else "free_kernel<ModelSIR>",
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": measured_traffic(["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
+                                                 spec.name),
+                     "kernel": ["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]] + "<ModelSIR>",
                      "ssa_steps_per_launch": draws_per_launch, "ops_per_step": OPS_PER_STEP},
     }
     if not args.no_cpu:
