@@ -236,6 +236,58 @@ int siminf_prevalence_quantiles(siminf_model *m, int32_t case_c, uint32_t at_ris
                                 int32_t replicates, int32_t k0, int32_t nk,
                                 const double *probs, int32_t nq, float *out, void *hip_stream);
 
+/* ---- surrogate network (BF16 matrix cores, FP32 accumulation) -------------
+ * A multilayer perceptron dims[0] -> dims[1] -> ... -> dims[nlayers]:
+ *   Z_l = A_{l-1} W_l^T + b_l,  A_l = GELU(Z_l) (exact erf form) for hidden
+ *   layers, output Y = Z_L.  Products take bfloat16 operands (inputs,
+ *   weights, activations, gradients, rounded to nearest even) and accumulate
+ *   in float32; master weights and optimiser state are float32.
+ * Training minimises the pinball (quantile) loss averaged over batch and
+ * outputs, mean max(q_j (t - y), (q_j - 1)(t - y)) with q_j = probs[j mod nq],
+ * using AdamW.  The network owns its device memory; X, T and Y are device
+ * pointers (float32, row-major [batch][features]).  Not thread-safe per handle. */
+typedef struct siminf_mlp siminf_mlp;
+
+/* Creates a network with zero weights for batches up to max_batch. */
+int siminf_mlp_create(int32_t nlayers, const int32_t *dims, int32_t max_batch, siminf_mlp **out);
+
+/* Sets layer `layer`'s weights W (dims[l+1] x dims[l], row-major, host
+ * float32) and bias b (host), refreshes the bfloat16 copy and resets the
+ * layer's optimiser state and the step count. */
+int siminf_mlp_set_params(siminf_mlp *m, int32_t layer, const float *W, const float *b);
+
+/* Copies the float32 master weights and bias of a layer to host memory. */
+int siminf_mlp_get_params(const siminf_mlp *m, int32_t layer, float *W, float *b);
+
+/* Y[B][dims[L]] = network(X[B][dims[0]]), enqueued on hip_stream. */
+int siminf_mlp_forward(siminf_mlp *m, const float *X, int32_t B, float *Y, void *hip_stream);
+
+/* Forward, pinball loss against targets T[B][dims[L]] at quantile levels
+ * probs[0..nq-1] (nq <= 8), and back-propagation; the gradients stay in the
+ * handle (siminf_mlp_get_grads, siminf_mlp_adamw).  If loss is not NULL the
+ * call waits and stores the mean loss there. */
+int siminf_mlp_backward(siminf_mlp *m, const float *X, const float *T, int32_t B, const double *probs,
+                        int32_t nq, double *loss, void *hip_stream);
+
+/* Copies the last computed gradients of a layer to host memory (waits). */
+int siminf_mlp_get_grads(const siminf_mlp *m, int32_t layer, float *dW, float *db);
+
+/* One AdamW step (decoupled weight decay) of every layer with the last
+ * gradients: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * w -= lr (m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps) + weight_decay w). */
+int siminf_mlp_adamw(siminf_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay,
+                     void *hip_stream);
+
+/* Frees the network (waits for the device). */
+void siminf_mlp_destroy(siminf_mlp *m);
+
+/* C[M][N] (float32, row stride ldc) = A B with bfloat16 operands (uint16_t
+ * bit patterns): A is M x K, stored A[m*lda + k] (a_trans = 0) or
+ * A[k*lda + m] (a_trans = 1); B is K x N, stored B[n*ldb + k] (b_trans = 0)
+ * or B[k*ldb + n] (b_trans = 1).  Device pointers; enqueued on hip_stream. */
+int siminf_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t lda, int32_t a_trans,
+                     const uint16_t *B, int32_t ldb, int32_t b_trans, float *C, int32_t ldc, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

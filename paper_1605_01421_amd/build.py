@@ -21,7 +21,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contr
              "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["ssa_kernels.hip", "runtime.cpp"]
+SOURCES = ["ssa_kernels.hip", "mlp.hip", "runtime.cpp"]
 
 
 def hipcc() -> str:

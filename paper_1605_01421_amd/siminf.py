@@ -68,6 +68,18 @@ SIGNATURES = {
     "siminf_prevalence_quantiles": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
                                                    ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                                    _P, _P]),
+    "siminf_mlp_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "siminf_mlp_set_params": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "siminf_mlp_get_params": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "siminf_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    "siminf_mlp_backward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P]),
+    "siminf_mlp_get_grads": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "siminf_mlp_adamw": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, _P]),
+    "siminf_mlp_destroy": (None, [_P]),
+    "siminf_gemm_bf16": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                        ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                        _P]),
 }
 
 _lib = None
@@ -310,3 +322,95 @@ def header_symbols(header_path: str) -> list:
     text = open(header_path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(siminf_[a-z_0-9]+)\s*\(", text)))
+
+
+class MLP:
+    """The surrogate network of the library (siminf_mlp_*): weights and
+    optimiser state live on the device; data are torch float32 CUDA tensors."""
+
+    def __init__(self, dims, max_batch: int):
+        lib = load()
+        self._lib = lib
+        self.dims = [int(d) for d in dims]
+        d = np.asarray(self.dims, dtype=np.int32)
+        self._h = ctypes.c_void_p()
+        rc = lib.siminf_mlp_create(len(self.dims) - 1, _ptr(d), int(max_batch), ctypes.byref(self._h))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_mlp_create")
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.siminf_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        for l, (W, b) in enumerate(params):
+            Wf = _c(W, np.float32)
+            bf = _c(b, np.float32)
+            rc = self._lib.siminf_mlp_set_params(self._h, l, _ptr(Wf), _ptr(bf))
+            if rc != SIMINF_OK:
+                raise SiminfError(rc, "siminf_mlp_set_params")
+
+    def get_params(self):
+        out = []
+        for l in range(len(self.dims) - 1):
+            W = np.empty((self.dims[l + 1], self.dims[l]), dtype=np.float32)
+            b = np.empty(self.dims[l + 1], dtype=np.float32)
+            rc = self._lib.siminf_mlp_get_params(self._h, l, _ptr(W), _ptr(b))
+            if rc != SIMINF_OK:
+                raise SiminfError(rc, "siminf_mlp_get_params")
+            out.append((W, b))
+        return out
+
+    def get_grads(self):
+        out = []
+        for l in range(len(self.dims) - 1):
+            W = np.empty((self.dims[l + 1], self.dims[l]), dtype=np.float32)
+            b = np.empty(self.dims[l + 1], dtype=np.float32)
+            rc = self._lib.siminf_mlp_get_grads(self._h, l, _ptr(W), _ptr(b))
+            if rc != SIMINF_OK:
+                raise SiminfError(rc, "siminf_mlp_get_grads")
+            out.append((W, b))
+        return out
+
+    def forward(self, X, Y=None, hip_stream=None):
+        import torch
+        B = X.shape[0]
+        if Y is None:
+            Y = torch.empty((B, self.dims[-1]), dtype=torch.float32, device=X.device)
+        rc = self._lib.siminf_mlp_forward(self._h, ctypes.c_void_p(X.data_ptr()), B,
+                                          ctypes.c_void_p(Y.data_ptr()), _stream_handle(hip_stream))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_mlp_forward")
+        return Y
+
+    def backward(self, X, T, probs=(0.1, 0.5, 0.9), want_loss=True, hip_stream=None):
+        p = _c(probs, np.float64)
+        loss = ctypes.c_double()
+        rc = self._lib.siminf_mlp_backward(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                           X.shape[0], _ptr(p), p.size,
+                                           ctypes.byref(loss) if want_loss else None, _stream_handle(hip_stream))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_mlp_backward")
+        return loss.value if want_loss else None
+
+    def adamw(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, hip_stream=None):
+        rc = self._lib.siminf_mlp_adamw(self._h, lr, beta1, beta2, eps, weight_decay, _stream_handle(hip_stream))
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_mlp_adamw")
+
+
+def gemm_bf16(A_bits, B_bits, M, N, K, lda, a_trans, ldb, b_trans, C, ldc, hip_stream=None):
+    """siminf_gemm_bf16 on torch int16/uint16 tensors holding bfloat16 bit patterns."""
+    rc = load().siminf_gemm_bf16(M, N, K, ctypes.c_void_p(A_bits.data_ptr()), lda, a_trans,
+                                 ctypes.c_void_p(B_bits.data_ptr()), ldb, b_trans,
+                                 ctypes.c_void_p(C.data_ptr()), ldc, _stream_handle(hip_stream))
+    if rc != SIMINF_OK:
+        raise SiminfError(rc, "siminf_gemm_bf16")

@@ -341,3 +341,14 @@ def ensemble_sets(seed: int = 3, n_sets: int = 64, replicates: int = 64, days: i
                           ls.mean(), ls.var(), np.log(Nn)], dtype=np.float64)
         sets.append(EnsembleSet(spec, replicates, feats))
     return sets
+
+
+def mlp_init(dims, seed):
+    """Initial surrogate weights: uniform on +-sqrt(6 / fan_in) (He-style),
+    zero biases; a list of (W (out, in), b (out,)) float64 arrays."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for i in range(len(dims) - 1):
+        lim = np.sqrt(6.0 / dims[i])
+        params.append((rng.uniform(-lim, lim, (dims[i + 1], dims[i])), np.zeros(dims[i + 1])))
+    return params

@@ -1,0 +1,127 @@
+"""GPU checks of the surrogate network kernels against the float64 oracle.
+
+The oracle rounds inputs, hidden activations and back-propagated gradients to
+bfloat16 at the same points as the kernels, so the remaining differences come
+from float32 accumulation and the float32 GELU; per-tensor relative Frobenius
+errors must stay below 2e-2 for gradients (5e-3 for the forward pass)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from paper_1605_01421_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 256, 256, 256, 256, 156)
+PROBS = (0.1, 0.5, 0.9)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1605_01421_amd import siminf
+    siminf.load()
+    return siminf
+
+
+def _relf(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _bf16_bits(x):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).cuda(), t.to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("a_trans,b_trans", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_orientations(lib, a_trans, b_trans):
+    import torch
+    rng = np.random.default_rng(a_trans * 2 + b_trans)
+    M, N, K = 70, 130, 45
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(K, N))
+    Astore = A.T if a_trans else A          # a_trans: stored K x M
+    Bstore = B if b_trans else B.T          # b_trans: stored K x N, else N x K
+    Ab, Aval = _bf16_bits(Astore)
+    Bb, Bval = _bf16_bits(Bstore)
+    Aeff = Aval.T if a_trans else Aval
+    Beff = Bval if b_trans else Bval.T
+    C = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    lib.gemm_bf16(Ab, Bb, M, N, K, Astore.shape[1], a_trans, Bstore.shape[1], b_trans, C, N)
+    torch.cuda.synchronize()
+    want = Aeff @ Beff
+    assert np.max(np.abs(C.cpu().numpy() - want)) <= 1e-5 * np.max(np.abs(want))
+
+
+def _setup(seed, B):
+    import torch
+    params = W.mlp_init(DIMS, seed)
+    rng = np.random.default_rng(seed + 100)
+    params = [(Wl, rng.normal(scale=0.1, size=b.shape)) for Wl, b in params]
+    X = rng.normal(size=(B, DIMS[0]))
+    T = rng.normal(scale=0.5, size=(B, DIMS[-1]))
+    # the values the device computes with: bfloat16 weights, float32 biases
+    rparams = [(ref.bf16(Wl), b.astype(np.float32).astype(np.float64)) for Wl, b in params]
+    Xt = torch.from_numpy(X.astype(np.float32)).cuda()
+    Tt = torch.from_numpy(T.astype(np.float32)).cuda()
+    return params, rparams, X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64), Xt, Tt
+
+
+def test_forward_matches_oracle(lib):
+    params, rparams, X, T, Xt, Tt = _setup(1, 300)
+    net = lib.MLP(DIMS, 512)
+    net.set_params(params)
+    Y = net.forward(Xt).cpu().numpy().astype(np.float64)
+    want, _ = ref.forward(rparams, X, round_bf16=True)
+    assert _relf(Y, want) < 5e-3
+
+
+def test_gradients_match_oracle(lib):
+    params, rparams, X, T, Xt, Tt = _setup(2, 257)
+    net = lib.MLP(DIMS, 512)
+    net.set_params(params)
+    loss = net.backward(Xt, Tt, PROBS)
+    wl, wgrads, _ = ref.loss_and_grads(rparams, X, T, PROBS, round_bf16=True)
+    assert abs(loss - wl) / wl < 1e-3
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(net.get_grads(), wgrads)):
+        assert _relf(gW.astype(np.float64), rW) < 2e-2, ("W", l)
+        assert _relf(gb.astype(np.float64), rb) < 2e-2, ("b", l)
+
+
+def test_adamw_matches_oracle(lib):
+    params, rparams, X, T, Xt, Tt = _setup(3, 128)
+    net = lib.MLP(DIMS, 256)
+    net.set_params(params)
+    master = [(Wl.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64))
+              for Wl, b in params]
+    state = ref.init_state(master)
+    for step in range(3):
+        net.backward(Xt, Tt, PROBS, want_loss=False)
+        g = [(a.astype(np.float64), b.astype(np.float64)) for a, b in net.get_grads()]
+        net.adamw(1e-3, weight_decay=0.01)
+        ref.adamw_step(master, g, state, 1e-3, weight_decay=0.01)
+        got = net.get_params()
+        for (gW, gb), (mW, mb) in zip(got, master):
+            assert np.allclose(gW, mW, rtol=1e-5, atol=1e-6)
+            assert np.allclose(gb, mb, rtol=1e-5, atol=1e-6)
+        master = [(a.astype(np.float64), b.astype(np.float64)) for a, b in got]
+
+
+def test_training_reduces_loss(lib):
+    import torch
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(512, 8)).astype(np.float32)
+    Wt = rng.normal(size=(8, 156)) / 3
+    T = (np.tanh(X @ Wt) + 0.05 * rng.normal(size=(512, 156))).astype(np.float32)
+    net = lib.MLP(DIMS, 512)
+    net.set_params(W.mlp_init(DIMS, 7))
+    Xt, Tt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    first = net.backward(Xt, Tt, PROBS)
+    net.adamw(2e-3)
+    for _ in range(300):
+        net.backward(Xt, Tt, PROBS, want_loss=False)
+        net.adamw(2e-3)
+    last = net.backward(Xt, Tt, PROBS)
+    assert last < 0.5 * first

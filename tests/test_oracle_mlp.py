@@ -1,0 +1,80 @@
+"""Pins for the float64 surrogate-network reference: finite differences,
+closed forms of GELU and the pinball loss, the first AdamW step, and
+bfloat16 rounding against torch's conversion."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+from oracle import mlp
+from paper_1605_01421_amd import workloads as W
+
+
+def test_gelu_closed_forms():
+    z = np.linspace(-6, 6, 121)
+    assert np.allclose(mlp.gelu(z), z * stats.norm.cdf(z), rtol=1e-14, atol=1e-300)
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    h = 1e-6
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.allclose(mlp.gelu_grad(z), fd, rtol=1e-7, atol=1e-9)
+
+
+def test_pinball_values_and_quantile_minimiser():
+    loss, g = mlp.pinball(np.array([[0.0, 1.0]]), np.array([[1.0, 0.0]]), (0.9,))
+    assert loss == pytest.approx((0.9 * 1 + 0.1 * 1) / 2)
+    assert np.allclose(g, [[-0.9 / 2, 0.1 / 2]])
+    # the constant minimising the mean pinball loss is the empirical quantile
+    rng = np.random.default_rng(0)
+    t = rng.normal(size=999)
+    grid = np.linspace(-3, 3, 6001)
+    for q in (0.1, 0.5, 0.9):
+        L = [np.mean(np.maximum(q * (t - c), (q - 1) * (t - c))) for c in grid]
+        best = grid[int(np.argmin(L))]
+        assert abs(best - np.quantile(t, q, method="inverted_cdf")) < 2e-3
+
+
+def test_gradients_match_central_differences():
+    dims = (3, 5, 4, 6)
+    params = W.mlp_init(dims, seed=4)
+    params = [(Wl, b + 0.1 * np.arange(len(b))) for Wl, b in params]
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(7, 3))
+    Y0, _ = mlp.forward(params, X)
+    T = Y0 + np.where(rng.random(Y0.shape) < 0.5, -1.0, 1.0) * (0.5 + rng.random(Y0.shape))
+    probs = (0.1, 0.5, 0.9)
+    loss, grads, _ = mlp.loss_and_grads(params, X, T, probs)
+    h = 1e-6
+    for l, (Wl, bl) in enumerate(params):
+        for arr, g in ((Wl, grads[l][0]), (bl, grads[l][1])):
+            num = np.zeros_like(arr)
+            it = np.nditer(arr, flags=["multi_index"])
+            for _ in it:
+                i = it.multi_index
+                old = arr[i]
+                arr[i] = old + h
+                lp = mlp.loss_and_grads(params, X, T, probs)[0]
+                arr[i] = old - h
+                lm = mlp.loss_and_grads(params, X, T, probs)[0]
+                arr[i] = old
+                num[i] = (lp - lm) / (2 * h)
+            assert np.allclose(g, num, rtol=1e-6, atol=1e-9), l
+
+
+def test_first_adamw_step_is_sign_step():
+    params = [(np.array([[1.0, -2.0]]), np.array([0.5]))]
+    grads = [(np.array([[0.3, -4.0]]), np.array([0.0]))]
+    st = mlp.init_state(params)
+    mlp.adamw_step(params, grads, st, lr=0.01, eps=0.0, weight_decay=0.1)
+    # m_hat = g, v_hat = g^2 on the first step -> update lr * (sign(g) + wd * w)
+    assert np.allclose(params[0][0], [[1.0 - 0.01 * (1 + 0.1), -2.0 - 0.01 * (-1 + 0.1 * -2.0)]])
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(size=5000) * 10.0 ** rng.integers(-6, 6, 5000),
+                        1 + np.arange(1, 64) * 2.0 ** -9, [0.0, -0.0, 1e30, -3.5]])
+    want = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16(x), want)
+    assert mlp.bf16(np.array([1 + 2 ** -8]))[0] == 1.0  # tie to even
