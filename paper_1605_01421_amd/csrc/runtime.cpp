@@ -414,19 +414,47 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         std::vector<int> grp_runs;
         for (int r = 0; r < m->R; ++r)
             if (m->runs[r].group == (int)gi) grp_runs.push_back(r);
+        // expected work of each node of each spec: individuals + 8 per event
+        std::vector<std::vector<int64_t>> spec_work(nspecs);
+        std::vector<std::vector<int32_t>> spec_order(nspecs);
         for (int r : grp_runs) {
-            const siminf_spec& s = specs[m->runs[r].spec];
-            std::vector<int64_t> nev(s.Nn, 0);
-            for (int e = 0; e < s.Nev; ++e) nev[s.ev_node[e]] += 1;
-            for (int i = 0; i < s.Nn; ++i) {
-                int64_t w = 0;
-                for (int c = 0; c < s.Nc; ++c) w += s.u0[(size_t)i * s.Nc + c];
-                nodes.push_back({r, i, w + 8 * nev[i]});
-            }
+            const int si = m->runs[r].spec;
+            if (!spec_work[si].empty() || specs[si].Nn == 0) continue;
+            const siminf_spec& s = specs[si];
+            std::vector<int64_t>& w = spec_work[si];
+            w.assign(s.Nn, 0);
+            for (int e = 0; e < s.Nev; ++e) w[s.ev_node[e]] += 8;
+            for (int i = 0; i < s.Nn; ++i)
+                for (int c = 0; c < s.Nc; ++c) w[i] += s.u0[(size_t)i * s.Nc + c];
+            std::vector<int32_t>& o = spec_order[si];
+            o.resize(s.Nn);
+            std::iota(o.begin(), o.end(), 0);
+            if (m->opt.order == 0)
+                std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
         }
-        if (m->opt.order == 0)
-            std::stable_sort(nodes.begin(), nodes.end(),
-                             [](const NodeRef& a, const NodeRef& b) { return a.work > b.work; });
+        if (m->opt.order == 0 && grp_runs.size() > 1) {
+            // batches: run-major, runs by their heaviest node (longest first on
+            // the work queue), each run's nodes by expected work; a wavefront
+            // then mostly holds nodes of one run with similar work
+            std::vector<int> runs_sorted = grp_runs;
+            auto top = [&](int r) {
+                const int si = m->runs[r].spec;
+                return spec_order[si].empty() ? (int64_t)0 : spec_work[si][spec_order[si][0]];
+            };
+            std::stable_sort(runs_sorted.begin(), runs_sorted.end(), [&](int a, int b) { return top(a) > top(b); });
+            for (int r : runs_sorted) {
+                const int si = m->runs[r].spec;
+                for (int32_t i : spec_order[si]) nodes.push_back({r, i, spec_work[si][i]});
+            }
+        } else {
+            for (int r : grp_runs) {
+                const int si = m->runs[r].spec;
+                for (int32_t i = 0; i < specs[si].Nn; ++i) nodes.push_back({r, i, spec_work[si][i]});
+            }
+            if (m->opt.order == 0)
+                std::stable_sort(nodes.begin(), nodes.end(),
+                                 [](const NodeRef& a, const NodeRef& b) { return a.work > b.work; });
+        }
         const int n = (int)nodes.size();
         g.n = n;
         g.work.resize(n);
