@@ -38,15 +38,18 @@ OPS_PER_STEP = 260
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
+SSA_SOURCES = ("device_math.h", "internal.h", "models.h", "runtime.cpp", "ssa_kernels.hip")
+
+
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources of the library (identifies a kernel build)."""
+    """sha256 over the sources that decide the SSA kernels' code and data
+    layout (the network's file is left out: it does not touch them)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1605_01421_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in SSA_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

@@ -137,6 +137,11 @@ typedef struct {
                           kernel, 2 dataflow kernel (node state in registers) */
     int32_t wide;      /* with lanes = 64: how many of the heaviest nodes get a
                           wavefront (0 = chosen from the expected work) */
+    int32_t wait_ms;   /* longest wall-clock time one wait inside a kernel (a
+                          grid barrier, or a destination waiting for its source's
+                          transfer) may take before the run is abandoned with
+                          SIMINF_E_DEVICE; 0 = 60000.  Legitimate waits can last
+                          as long as the slowest node's share of the run. */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;
@@ -146,7 +151,9 @@ typedef struct siminf_model siminf_model;
  * Static event errors are reported here: SIMINF_E_EVENT_INDEX for a node,
  * dest, select or shift out of range (also a shift target outside 0..Nc-1
  * for any selected compartment); siminf_error_info then names the event.
- * Limits: Nc <= 16, Nt <= 32, Ecols <= 1<<20, Ntspan >= 1, Nn >= 0. */
+ * Shape: Nc, Nt and Nv must equal the built-in model's (SIR 3/2/0, SIS 2/2/0,
+ * SISe 2/2/1, birth-death and immigration-death 1/2/0; anything else is
+ * SIMINF_E_ARG), Nld and Ngd at least the model's; Ntspan >= 1, Nn >= 0. */
 int siminf_create(const siminf_spec *spec, const siminf_options *opt, siminf_model **out);
 
 /* A batch: specs[s] is run replicates[s] times (run r of the batch uses

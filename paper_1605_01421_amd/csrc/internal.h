@@ -108,6 +108,7 @@ struct KParams {
     int32_t pipeline;            // 1: overlap the next step's random numbers with this step
     int32_t nbig;                // the first nbig nodes each get a whole wavefront
     int32_t pad2;
+    uint64_t wait_ticks;         // wall-clock ticks one wait may last before abort
 };
 
 // Launchers implemented in ssa_kernels.hip.

@@ -167,6 +167,16 @@ int device_cus(const siminf_model* m) {
     return cus;
 }
 
+// Wall-clock ticks one in-kernel wait may last (options.wait_ms, default 60 s),
+// at the rate of the device's constant real-time counter.
+uint64_t wait_ticks(const siminf_model* m) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, m->device) != hipSuccess || khz <= 0)
+        khz = 100000;
+    const int64_t ms = m->opt.wait_ms > 0 ? m->opt.wait_ms : 60000;
+    return (uint64_t)khz * (uint64_t)ms;
+}
+
 // Heaviest nodes worth a whole wavefront each.  A wide node runs its steps
 // about twice as fast as a node sharing its wavefront with 63 others but
 // occupies 64 lanes, so only nodes that would otherwise set the critical path
@@ -261,7 +271,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
-    if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2) {
+    if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2 || m->opt.wait_ms < 0) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -635,6 +645,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         };
         KParams& p = g.p;
         p = KParams{};
+        p.wait_ticks = wait_ticks(m);
         p.n = n;
         p.nb = m->nb;
         p.ntspan = m->ntspan;

@@ -17,7 +17,8 @@
 //    lanes meet at a grid barrier on every day with transfers; workgroup 0
 //    applies them level by level in global memory; a second barrier follows.
 // The flow and sync kernels are launched cooperatively (all workgroups
-// resident).  Every wait has a spin limit that turns a stall into an error.
+// resident).  Every wait has a wall-clock limit that turns a stall into an
+// error.
 #include "device_math.h"
 #include "internal.h"
 #include "models.h"
@@ -31,7 +32,7 @@ namespace {
 
 constexpr int E_NEG_STATE = -5, E_BAD_RATE = -6, E_OVERDRAW = -7, E_PTS = -9;
 constexpr int EV_EXIT = 0, EV_ENTER = 1, EV_EXTTRANS = 3;
-constexpr unsigned SPIN_LIMIT = 1u << 22;
+
 // Transitions of one node within one unit of time beyond which the rates are
 // declared unusable (time would no longer advance at binary64 resolution).
 constexpr uint32_t STEP_LIMIT = 1u << 24;
@@ -39,6 +40,20 @@ constexpr uint32_t STEP_LIMIT = 1u << 24;
 __device__ __forceinline__ void raise_error(Ctrl* c, int step, int phase, int64_t ord, int code) {
     atomicMin(&c->err_key, make_err_key((uint32_t)step, (uint32_t)phase, (uint64_t)ord, (uint32_t)(-code)));
 }
+
+// Wall-clock limit of one wait: the constant-rate real-time counter is read
+// every 256 polls; the first read starts the clock.
+struct WaitClock {
+    uint64_t start = 0;
+    __device__ __forceinline__ bool expired(uint64_t limit) {
+        const uint64_t now = (uint64_t)wall_clock64();
+        if (start == 0) {
+            start = now | 1ull;
+            return false;
+        }
+        return now - start > limit;
+    }
+};
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
 #pragma unroll
@@ -55,29 +70,6 @@ __device__ __forceinline__ uint64_t error_step(Ctrl* c) {
     uint64_t k = 0;
     if ((threadIdx.x & (WAVE - 1)) == 0) k = load_error_step(c);
     return __shfl(k, 0, WAVE);
-}
-
-// Waits until *flag >= target.  Polls with relaxed loads (no cache
-// maintenance per poll), checks for an abort or an earlier step's error every
-// 256 polls, and issues one acquire fence once the target is reached.  After
-// SPIN_LIMIT polls it sets abort so that every other wait ends too.  Returns
-// true if the target was reached.
-__device__ __forceinline__ bool wait_at_least(unsigned int* flag, unsigned target, Ctrl* c, int step,
-                                              bool fence = true) {
-    unsigned spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if ((++spins & 255u) == 0) {
-            if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-            if (load_error_step(c) < (uint64_t)step) return false;
-            if (spins > SPIN_LIMIT) {
-                __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return false;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    if (fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
 }
 
 template <class M>
@@ -532,6 +524,7 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams p) {
         // sources never wait, so no lane can block another one of its wave.
         bool pending = active && item.y == b;
         unsigned spins = 0;
+        WaitClock clock;
         while (__any(pending)) {
             bool moved = false;
             if (pending) {
@@ -578,9 +571,11 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams p) {
                 if ((++spins & 255u) == 0) {
                     const bool quit = __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                                       load_error_step(p.ctrl) < (uint64_t)b;
-                    if (spins > SPIN_LIMIT && lane == 0)
+                    // wave-uniform: every lane reads the same counter word
+                    const bool late = __shfl(clock.expired(p.wait_ticks) ? 1 : 0, 0, WAVE) != 0;
+                    if (late && lane == 0)
                         __hip_atomic_store(&p.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (__any(quit) || spins > SPIN_LIMIT) break;
+                    if (__any(quit) || late) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
@@ -602,16 +597,17 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams p) {
 // ---------------------------------------------------------------------------
 // Grid barrier on a monotone arrival counter: the epoch-th barrier completes
 // when epoch * gridDim.x workgroups have arrived.
-__device__ __forceinline__ void grid_barrier(Ctrl* c, unsigned epoch) {
+__device__ __forceinline__ void grid_barrier(Ctrl* c, unsigned epoch, uint64_t limit) {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned target = epoch * gridDim.x;
         __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
+        WaitClock clock;
         while (__hip_atomic_load(&c->bar_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            if (++spins > SPIN_LIMIT) {
+            if ((++spins & 255u) == 0 && clock.expired(limit)) {
                 __hip_atomic_store(&c->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -674,7 +670,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
         }
         if (!e2day) continue;
 
-        grid_barrier(p.ctrl, ++epoch);
+        grid_barrier(p.ctrl, ++epoch, p.wait_ticks);
         if (blockIdx.x == 0) {
             // this step's transfers, level by level in key order; the branch
             // and the level loop are uniform over workgroup 0
@@ -711,7 +707,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams p) {
                 __syncthreads();
             }
         }
-        grid_barrier(p.ctrl, ++epoch);
+        grid_barrier(p.ctrl, ++epoch, p.wait_ticks);
 
         for (int base = wave_base; base < p.n; base += nthreads) {
             const int k = base + lane;

@@ -241,3 +241,21 @@ def test_autotune_keeps_bits(lib):
     m.run(77, 2)
     assert m.wait() == 0
     _compare(m, ref, what=f"autotuned {m.launch_info()}")
+
+
+def test_wait_limit_abandons_run_cleanly(lib):
+    """A destination that must wait longer than options.wait_ms for its
+    source ends the run with SIMINF_E_DEVICE (node 0 makes about 10^6
+    transitions on day 1 before it can send; node 1 waits for it with a 1 ms
+    limit).  Every kernel exits normally, and a model with the default limit
+    then reproduces the oracle."""
+    u0 = np.array([[500000, 500000, 0], [10, 0, 0]])
+    ev = W.make_events([(W.EXTTRANS, 1, 0, 1, 1, 0.0, 0, -1)])
+    spec = W.sir_spec(u0, [0, 1, 2], 1.0, 1.0, events=ev)
+    m = lib.Model(spec, mode=2, wait_ms=1)
+    _say("wait limit 1 ms", m.launch_info())
+    m.run(3, 0)
+    assert m.wait() == -4
+    m2, ref, rc = _run_both(lib, spec, 3, 0, mode=2)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m2, ref, what="after an abandoned run")
