@@ -137,6 +137,9 @@ typedef struct {
                           kernel, 2 dataflow kernel (node state in registers) */
     int32_t wide;      /* with lanes = 64: how many of the heaviest nodes get a
                           wavefront (0 = chosen from the expected work) */
+    int32_t lattice;   /* wavefront-wide nodes: 0 auto (on when G marks both rates
+                          after either transition), 1 the same, 2 off (every
+                          step on one dependent chain); the results are equal */
     int32_t wait_ms;   /* longest wall-clock time one wait inside a kernel (a
                           grid barrier, or a destination waiting for its source's
                           transfer) may take before the run is abandoned with

@@ -53,6 +53,13 @@
 #define OR_E_PTS (-9)
 
 /* phases of one unit of time, in the order of Appendix A */
+/* Reading of the method for runaway rates: a node that would need a draw
+ * with index OR_STEP_LIMIT (counted from 0) within one day step is stopped
+ * with E_BAD_RATE, checked after the lambda test and before the draw.  The
+ * paper's algorithm has no such guard; it bounds the loop when the rates are
+ * so large that tau no longer advances t at binary64 resolution. */
+#define OR_STEP_LIMIT (1u << 24)
+
 #define PH_SSA 0
 #define PH_E1 1
 #define PH_E2 2
@@ -583,6 +590,10 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
                     lambda = lambda + w[j];
                 if (!(lambda > 0.0))
                     break; /* nothing can happen: time moves to T */
+                if (k == OR_STEP_LIMIT) {
+                    bad = OR_E_BAD_RATE;
+                    break;
+                }
                 uint32_t r[4];
                 ctr[0] = k++;
                 oracle_philox(key, ctr, r);

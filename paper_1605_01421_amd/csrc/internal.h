@@ -107,7 +107,7 @@ struct KParams {
     int32_t nblocks;
     int32_t pipeline;            // 1: overlap the next step's random numbers with this step
     int32_t nbig;                // the first nbig nodes each get a whole wavefront
-    int32_t pad2;
+    int32_t lattice;             // wide nodes walk a lattice of reachable states
     uint64_t wait_ticks;         // wall-clock ticks one wait may last before abort
 };
 

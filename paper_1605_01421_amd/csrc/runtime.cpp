@@ -177,20 +177,21 @@ uint64_t wait_ticks(const siminf_model* m) {
     return (uint64_t)khz * (uint64_t)ms;
 }
 
-// Heaviest nodes worth a whole wavefront each.  A wide node runs its steps
-// about twice as fast as a node sharing its wavefront with 63 others but
-// occupies 64 lanes, so only nodes that would otherwise set the critical path
-// qualify: expected work above a fifth of the heaviest node's and above the
-// share of the whole run one lane would get if the work were spread evenly
-// over 34,560 lanes (the measured throughput of the device in lane-steps per
-// lane-step time).  Needs the binned (work-sorted) node order.
-int default_wide(const siminf_model* m, const Group& g) {
+// Heaviest nodes worth a whole wavefront each.  A wide node walks its
+// steps several times faster than a node sharing its wavefront with 63
+// others but occupies 64 lanes, so only nodes that would otherwise set the
+// critical path qualify: expected work above 1/div of the heaviest node's and
+// above the share of the whole run one lane would get if the work were
+// spread evenly over 34,560 lanes (the measured throughput of the device in
+// lane-steps per lane-step time).  Needs the binned (work-sorted) node order.
+int default_wide(const siminf_model* m, const Group& g, int div = 16) {
     if (m->opt.lanes == 1 || g.n == 0 || m->opt.order == 1) return 0;
     if (m->opt.lanes == 64 && m->opt.wide > 0) return std::min(m->opt.wide, g.n);
+    if (div <= 0) return 0;
     const int64_t top = g.work[0];
     long double total = 0;
     for (int64_t w : g.work) total += (long double)w;
-    const long double cut = std::max((long double)top / 5.0L, total / 34560.0L);
+    const long double cut = std::max((long double)top / (long double)div, total / 34560.0L);
     int nb = 0;
     while (nb < g.n && nb < 4096 && (long double)g.work[nb] > cut) ++nb;
     return nb;
@@ -271,7 +272,8 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
-    if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2 || m->opt.wait_ms < 0) {
+    if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2 || m->opt.wait_ms < 0 ||
+        m->opt.lattice < 0 || m->opt.lattice > 2) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -424,7 +426,12 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         std::vector<int> grp_runs;
         for (int r = 0; r < m->R; ++r)
             if (m->runs[r].group == (int)gi) grp_runs.push_back(r);
-        // expected work of each node of each spec: individuals + 8 per event
+        // expected work of each node of each spec: the larger of its initial
+        // and its mean population over the run, plus 8 per event it takes
+        // part in.  The mean counts every scheduled change from the day after
+        // it applies (a change given as a proportion is priced at the initial
+        // population): transfers can make a node that starts small the
+        // heaviest of all, while an epidemic in a large node is heaviest early.
         std::vector<std::vector<int64_t>> spec_work(nspecs);
         std::vector<std::vector<int32_t>> spec_order(nspecs);
         for (int r : grp_runs) {
@@ -432,10 +439,30 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
             if (!spec_work[si].empty() || specs[si].Nn == 0) continue;
             const siminf_spec& s = specs[si];
             std::vector<int64_t>& w = spec_work[si];
-            w.assign(s.Nn, 0);
-            for (int e = 0; e < s.Nev; ++e) w[s.ev_node[e]] += 8;
+            std::vector<double> pop(s.Nn, 0.0), popdays(s.Nn, 0.0);
             for (int i = 0; i < s.Nn; ++i)
-                for (int c = 0; c < s.Nc; ++c) w[i] += s.u0[(size_t)i * s.Nc + c];
+                for (int c = 0; c < s.Nc; ++c) pop[i] += s.u0[(size_t)i * s.Nc + c];
+            const double nbd = std::max(1, m->nb);
+            for (int i = 0; i < s.Nn; ++i) popdays[i] = pop[i] * nbd;
+            std::vector<int64_t> touches(s.Nn, 0);
+            for (int e = 0; e < s.Nev; ++e) {
+                const int ty = s.ev_type[e], src = s.ev_node[e];
+                touches[src] += 1;
+                if (ty == SIMINF_EXTTRANS) touches[s.ev_dest[e]] += 1;
+                const int64_t step = std::max<int64_t>(0, (int64_t)s.ev_time[e] - m->T1);
+                if (step >= m->nb || ty == SIMINF_INTTRANS) continue;
+                const double days = nbd - 1.0 - (double)step;
+                const double moved = s.ev_n[e] > 0 ? (double)s.ev_n[e] : s.ev_prop[e] * pop[src];
+                if (ty == SIMINF_ENTER) {
+                    popdays[src] += moved * days;
+                } else {
+                    popdays[src] -= moved * days;
+                    if (ty == SIMINF_EXTTRANS) popdays[s.ev_dest[e]] += moved * days;
+                }
+            }
+            w.assign(s.Nn, 0);
+            for (int i = 0; i < s.Nn; ++i)
+                w[i] = (int64_t)std::max(pop[i], popdays[i] / nbd) + 8 * touches[i];
             std::vector<int32_t>& o = spec_order[si];
             o.resize(s.Nn);
             std::iota(o.begin(), o.end(), 0);
@@ -659,6 +686,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 if (sp.G[k + (size_t)j * g.shape.nt]) mask |= 1u << k;
             p.Gmask[j] = mask;
         }
+        p.lattice = m->opt.lattice != 2 && g.shape.nt == 2 && p.Gmask[0] == 3u && p.Gmask[1] == 3u ? 1 : 0;
         int32_t *d_u0, *d_nrun, *d_nidx, *d_e1off, *d_e2step, *d_e2lvl, *d_e2noff;
         double *d_v0, *d_ld;
         int64_t* d_nord;
@@ -917,20 +945,19 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     if (m->groups.empty()) return SIMINF_OK;
     finish(m);
     struct Cand {
-        int block, wide_scale, pipeline;
+        int block, wide_div, pipeline;
     };
     std::vector<Cand> cands;
     for (int block : {64, 128, 256})
-        for (int scale : {0, 1, 2, 4})  // wide nodes: none, half, the default, twice the default
-            for (int pipe : {1, 2}) cands.push_back({block, scale, pipe});
+        for (int div : {0, 4, 16, 64})  // wide nodes: none, or work above 1/div of the heaviest
+            for (int pipe : {1, 2}) cands.push_back({block, div, pipe});
     double best = 1e300;
     Cand pick = cands[0];
     bool any = false;
     for (const Cand& c : cands) {
         bool ok = true;
         for (Group& g : m->groups) {
-            const int h = default_wide(m, g);
-            const int nb = c.wide_scale == 0 ? 0 : c.wide_scale == 1 ? h / 2 : c.wide_scale == 2 ? h : 2 * h;
+            const int nb = default_wide(m, g, c.wide_div);
             if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode) != SIMINF_OK) ok = false;
         }
         if (!ok) continue;
@@ -954,9 +981,7 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     }
     if (!any) return SIMINF_E_DEVICE;
     for (Group& g : m->groups) {
-        const int h = default_wide(m, g);
-        const int nb = pick.wide_scale == 0 ? 0 : pick.wide_scale == 1 ? h / 2 : pick.wide_scale == 2 ? h : 2 * h;
-        configure(m, g, pick.block, nb, pick.pipeline, m->opt.mode);
+        configure(m, g, pick.block, default_wide(m, g, pick.wide_div), pick.pipeline, m->opt.mode);
     }
     if (best_ms) *best_ms = best;
     return SIMINF_OK;

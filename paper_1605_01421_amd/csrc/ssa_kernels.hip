@@ -229,6 +229,123 @@ __device__ __forceinline__ int ssa_wide(const KParams& p, Node<M>& s, double t, 
     }
 }
 
+// Steps per window of the lattice walk, and the lanes its points occupy.
+constexpr int LAT_W = 10;
+constexpr int LAT_POINTS = LAT_W * (LAT_W + 1) / 2;
+static_assert(LAT_POINTS <= WAVE, "the lattice must fit one wavefront");
+
+// The same SSA for one heavy node on a whole wavefront, with the serial chain
+// cut to a few instructions per step.  With two transitions, the state k
+// steps ahead is u + a S[:,0] + (k - a) S[:,1] for some 0 <= a <= k.  One
+// wavefront-wide pass evaluates, for every lattice point (k, a) of the next
+// LAT_W steps at once, all that a step computes from its state: the checks
+// of the state, the rates, lambda, tau = E_k / lambda (E_k is the
+// exponential variate of step k), and the inversion choice with r2_k.  The
+// walk then follows the realised path: per step it reads tau and the choice
+// from the lane of the current point, advances t by one addition and stops
+// at the day boundary.  Every value comes from the same operations in the
+// same order as in ssa_to_boundary, so the result is bit-identical.  Valid
+// when G marks both rates after either transition: a full recomputation
+// then equals the incremental one.
+template <class M>
+__device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double t, double T, uint32_t day_word,
+                                           uint32_t node, uint32_t stream, unsigned long long& transitions,
+                                           unsigned long long& draws) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    int lk = 0;
+    while ((lk + 1) * (lk + 2) / 2 <= lane) ++lk;
+    const int la = lane - lk * (lk + 1) / 2;
+    const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
+    const uint32_t tag = stream & 0xFFFFFFu;
+    int32_t S0[M::NC], S1[M::NC];
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c) {
+        S0[c] = p.S[c];
+        S1[c] = p.S[c + M::NC];
+    }
+    uint32_t nd = 0, ntr = 0;  // draws and transitions, wave-uniform
+    int rc = 0;
+    bool done = false;
+    for (uint32_t base = 0; !done; base += WAVE) {
+        const StepRandoms mine = step_randoms(k0, k1, base + (uint32_t)lane, day_word, node, tag);
+        for (int off = 0; off < WAVE; off += LAT_W) {
+            const int wlen = WAVE - off < LAT_W ? WAVE - off : LAT_W;
+            // the pass: lane (lk, la) evaluates the state lk steps ahead with
+            // la transitions of the first kind
+            const int src = off + (lk < wlen ? lk : 0);
+            const double e = __shfl(mine.e, src, WAVE);
+            const double r2 = __shfl(mine.r2, src, WAVE);
+            int32_t uc[M::NC];
+            bool neg = false;
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) {
+                uc[c] = s.u[c] + la * S0[c] + (lk - la) * S1[c];
+                neg |= uc[c] < 0;
+            }
+            const double c0 = M::template rate<0>(uc, s.v, s.ld, s.gd);
+            const double c1 = M::template rate<1>(uc, s.v, s.ld, s.gd);
+            double lam = 0.0;
+            lam = lam + c0;
+            lam = lam + c1;
+            const double tau = e / lam;
+            const double x = lam * r2;
+            const int n = (c0 > 0.0 && x <= c0) ? 0 : (c1 > 0.0 ? 1 : 0);
+            // checks of the state: 1 a negative compartment, 2 a bad rate,
+            // 4 lambda <= 0 (the node stops for the day)
+            const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
+            const int to = (lk + 1) * (lk + 2) / 2 + la + (n == 0 ? 1 : 0);
+            const int chk_to = __shfl(chk, to < WAVE ? to : 0, WAVE);
+            const int word = n | (chk_to << 1);
+            // the window's first state (the day's starting state or the one
+            // the previous window ended in) is checked before its draw
+            const int c00 = __builtin_amdgcn_readfirstlane(chk);
+            if (c00) {
+                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
+                done = true;
+                break;
+            }
+            if (base + (uint32_t)off == STEP_LIMIT) {
+                rc = E_BAD_RATE;
+                done = true;
+                break;
+            }
+            // the walk: k steps taken, a of them of the first kind
+            int a = 0, k = 0, fail = 0;
+            bool boundary = false;
+            for (; k < wlen; ++k) {
+                const int L = k * (k + 1) / 2 + a;
+                ++nd;
+                const double tn = t + read_lane(tau, L);
+                if (tn >= T) {
+                    boundary = true;
+                    break;
+                }
+                t = tn;
+                const int w = __builtin_amdgcn_readlane(word, L);
+                a += (w & 1) ? 0 : 1;
+                ++ntr;
+                if (k + 1 < wlen && (w >> 1)) {
+                    fail = w >> 1;
+                    ++k;
+                    break;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) s.u[c] += a * S0[c] + (k - a) * S1[c];
+            if (boundary || fail) {
+                rc = (fail & 1) ? E_NEG_STATE : (fail & 2) ? E_BAD_RATE : 0;
+                done = true;
+                break;
+            }
+        }
+    }
+    if (lane == 0) {
+        draws += nd;
+        transitions += ntr;
+    }
+    return rc;
+}
+
 // One scheduled event (section 3.3) from its packed record, on node state u
 // (and destination ud for an external transfer).  Indices were validated
 // when the model was created.  Returns 0 or E_OVERDRAW (state unchanged).
@@ -380,8 +497,10 @@ __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, 
                                            bool& dead, Tally& t, bool wide) {
     const double T = (double)day;
     const double t0 = b == 0 ? p.t0 : T - 1.0;
-    int rc = wide ? ssa_wide<M>(p, s, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr)
-                  : ssa_to_boundary<M, PIPE>(p, s, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr);
+    const uint32_t dw = (uint32_t)(int32_t)day;
+    int rc = !wide       ? ssa_to_boundary<M, PIPE>(p, s, t0, T, dw, node, stream, t.tr, t.dr)
+             : p.lattice ? ssa_lattice<M>(p, s, t0, T, dw, node, stream, t.tr, t.dr)
+                         : ssa_wide<M>(p, s, t0, T, dw, node, stream, t.tr, t.dr);
     if (rc) {
         raise_error(p.ctrl, b, PH_SSA, ord, rc);
         dead = true;

@@ -118,7 +118,9 @@ def test_other_models(lib, kind):
                                   dict(mode=2, block=128), dict(pipeline=1), dict(pipeline=2),
                                   dict(mode=1, pipeline=2), dict(max_blocks=1, block=64),
                                   dict(lanes=1), dict(lanes=64, wide=1), dict(lanes=64, wide=40),
-                                  dict(lanes=64, wide=600, block=256), dict(lanes=64, wide=7, block=128, pipeline=2)])
+                                  dict(lanes=64, wide=600, block=256), dict(lanes=64, wide=7, block=128, pipeline=2),
+                                  dict(lanes=64, wide=600, lattice=2), dict(lanes=64, wide=600, mode=1, lattice=1),
+                                  dict(lanes=64, wide=90, block=64, lattice=2)])
 def test_launch_shape_does_not_change_bits(lib, opts):
     spec = W.config1(seed=11, Nn=600, days=50)
     ref = oracle_run(spec, 5, 0)
@@ -259,3 +261,45 @@ def test_wait_limit_abandons_run_cleanly(lib):
     m2, ref, rc = _run_both(lib, spec, 3, 0, mode=2)
     assert rc == 0 and ref["status"] == 0
     _compare(m2, ref, what="after an abandoned run")
+
+
+@pytest.mark.parametrize("lattice", [1, 2])
+@pytest.mark.parametrize("case", ["extinction", "immigration", "sise", "sir_heavy", "neg_state", "bad_rate",
+                                  "step_limit"])
+def test_wide_node_paths(lib, case, lattice):
+    """Every node on its own wavefront (lanes=64, wide=Nn), with the lattice
+    walk (1) and the plain dependent chain (2): stops at lambda = 0 inside a
+    window, thousands of steps per day, the SISe rates, an epidemic's
+    turnover, a negative compartment after a transition, a bad rate, and the
+    2^24-step guard, all against the oracle (state, counters, error key)."""
+    rng = np.random.default_rng(17)
+    tspan = np.arange(0, 6)
+    if case == "extinction":
+        spec = W.birth_death_spec(rng.integers(50, 400, 40), tspan, 0.5, 1.2)
+    elif case == "immigration":
+        spec = W.birth_death_spec(rng.integers(0, 10, 20), tspan, 3000.0, 0.7, immigration=True)
+    elif case == "sise":
+        spec = W.sise_spec(np.stack([rng.integers(1000, 20000, 20), rng.integers(0, 3000, 20)], 1),
+                           np.arange(0, 40), 0.0175, 0.1, 1.0, (0.1, 0.12, 0.1, 0.11))
+    elif case == "sir_heavy":
+        spec = W.sir_spec(np.stack([rng.integers(2000, 9000, 20), rng.integers(1, 50, 20),
+                                    np.zeros(20, int)], 1), np.arange(0, 60), 0.3, 0.1)
+    elif case == "neg_state":
+        spec = W.sir_spec(np.array([[500, 20, 0], [300, 4, 3]]), tspan, 0.4, 0.1)
+        spec.S = np.array([[-1, 0], [1, -1], [-1, 1]])   # an infection also removes a recovered
+    elif case == "bad_rate":
+        spec = W.sir_spec(np.array([[500, 20, 0], [300, 4, 3]]), tspan, -0.4, 0.1)
+    else:
+        spec = W.birth_death_spec(np.array([0, 0]), np.arange(0, 2), 3.0e7, 0.0, immigration=True)
+    Nn = np.asarray(spec.u0).shape[0]
+    m, ref, rc = _run_both(lib, spec, 23, 4, lanes=64, wide=Nn, lattice=lattice)
+    info = m.launch_info()
+    assert info["wide"] == Nn
+    assert rc == ref["status"]
+    if rc:
+        e = m.error_info()
+        assert (e["code"], e["step"], e["phase"], e["index"]) == ref["error"]
+        return
+    _compare(m, ref, what=case)
+    c = m.counters()
+    assert (c["transitions"], c["node_days"]) == (ref["transitions"], ref["node_days"])

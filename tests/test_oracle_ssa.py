@@ -253,3 +253,18 @@ def test_split_run_equals_full_run(orc):
     s2 = orc.run(W.sise_spec(s1["U"][-1], np.arange(40, 91), 0.02, 0.1, 1.0,
                              (0.1, 0.12, 0.1, 0.11), phi0=s1["V"][-1, :, 0]), 3, 0)
     assert np.array_equal(fa["U"][40:], s2["U"]) and np.array_equal(fa["V"][40:], s2["V"])
+
+
+def test_step_guard(orc):
+    """Immigration without death: X(1) ~ Poisson(kappa) exactly.  Below the
+    2^24-draw guard the count is Poisson (within 6 sd); above it the node
+    stops with E_BAD_RATE at the first day step, keyed to node 0."""
+    ok = W.birth_death_spec(np.array([0]), [0.0, 1.0], 1.0e7, 0.0, immigration=True)
+    r = orc.run(ok, seed=4, stream=0, nthreads=1)
+    assert r["status"] == 0
+    x = int(r["U"][-1, 0, 0])
+    assert abs(x - 1.0e7) < 6 * np.sqrt(1.0e7)
+    big = W.birth_death_spec(np.array([0, 0]), [0.0, 1.0], 3.0e7, 0.0, immigration=True)
+    r = orc.run(big, seed=4, stream=0, nthreads=2)
+    assert r["status"] == -6                      # E_BAD_RATE
+    assert r["error"] == (-6, 0, 0, 0)            # (code, day step, phase SSA, node 0)
