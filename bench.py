@@ -73,15 +73,53 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+MODEL_NAMES = {0: "SIR", 1: "SIS", 2: "SISe", 3: "birth-death", 4: "immigration-death"}
+
+
 def build_workload(name):
+    """(model argument, description) of a named workload: one run (a spec) or
+    a batch ([(spec, replicates)])."""
     from paper_1605_01421_amd import workloads as W
     if name == "sir-events":
-        return W.config1()
-    if name == "sir-plain":
-        return W.config0()
-    if name == "sise-events":
-        return W.config2()
-    raise SystemExit(f"unknown workload {name}")
+        spec = W.config1()
+    elif name == "sir-plain":
+        spec = W.config0()
+    elif name == "sise-events":
+        spec = W.config2()
+    elif name == "ensemble":
+        sets = W.ensemble_sets(seed=3, n_sets=64, replicates=64)
+        nodes = sum(s.spec.Nn for s in sets) * 64
+        desc = {"workload": "ensemble-64x64-365d", "runs": 64 * 64, "parameter_sets": 64, "replicates": 64,
+                "nodes": nodes, "days": 365, "scheduled_events": 0, "model": "SIR (32 sets) + SISe (32 sets)",
+                "record": "weekly sums per run"}
+        return [(s.spec, 64) for s in sets], desc
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    desc = {"workload": spec.name, "nodes": spec.Nn, "days": spec.n_days,
+            "scheduled_events": int(len(spec.events["time"])), "model": MODEL_NAMES[int(spec.model)],
+            "record": "U every day"}
+    return spec, desc
+
+
+def cpu_baseline_batch(batch, seed, seconds, gpu_sums):
+    """The oracle on the first runs of a batch (run r uses stream r), until
+    the time budget is spent; checks their weekly sums against the GPU's."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    runs, node_days, t_total, parity, r = 0, 0, 0.0, True, 0
+    flat = [spec for spec, reps in batch for _ in range(reps)]
+    while t_total < seconds and r < len(flat):
+        t0 = time.perf_counter()
+        out = oracle.run(flat[r], seed, r, nthreads=threads)
+        t_total += time.perf_counter() - t0
+        sums = out["U"].astype("int64").sum(axis=1)
+        parity = parity and bool((gpu_sums[r, :, :sums.shape[1]] == sums).all())
+        node_days += out["node_days"]
+        runs += 1
+        r += 1
+    return {"value": node_days / t_total, "unit": "node-days/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {runs} of {len(flat)} runs of the batch (seed {seed}, streams 0..{runs - 1}), "
+                      f"{t_total:.1f} s of CPU time", "sums_match_gpu": parity}
 
 
 def cpu_baseline(spec, seed, seconds, gpu_counters):
@@ -133,9 +171,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    spec = build_workload(args.workload)
-    model = siminf.Model(spec, block=args.block, order=args.order, lanes=args.lanes, wide=args.wide,
-                         pipeline=args.pipeline)
+    spec, desc = build_workload(args.workload)
+    batch = isinstance(spec, list)
+    model = siminf.Model(spec, record=siminf.RECORD_SUMS if batch else siminf.RECORD_FULL, block=args.block,
+                         order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline)
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
@@ -186,11 +225,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": spec.name, "nodes": spec.Nn, "days": spec.n_days,
-                   "scheduled_events": int(len(spec.events["time"])), "model": "SIR",
-                   "record": "U every day", "seed": seed0, "block": info["block"], "blocks": info["blocks"],
-                   "kernel": ["free-running", "grid-barrier", "dataflow"][info["mode"]],
-                   "wide_nodes": info["wide"], "pipeline": info["pipeline"]},
+        "config": dict(desc, seed=seed0, block=info["block"], blocks=info["blocks"],
+                       kernel=["free-running", "grid-barrier", "dataflow"][info["mode"]],
+                       wide_nodes=info["wide"], pipeline=info["pipeline"]),
         "transitions_per_s": transitions / wall,
         "events_per_step": events / args.steps,
         "kernel_ms_mean": mean_kernel_s * 1e3,
@@ -198,12 +235,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": measured_traffic(["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
-                                                 spec.name),
-                     "kernel": ["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]] + "<ModelSIR>",
+                                                 desc["workload"]),
+                     "kernel": ["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
                      "ssa_steps_per_launch": draws_per_launch, "ops_per_step": OPS_PER_STEP},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(spec, seed0, args.cpu_seconds, first_counters)
+        if batch:
+            out["cpu_baseline"] = cpu_baseline_batch(spec, seed0 + args.steps - 1, args.cpu_seconds, model.sums())
+        else:
+            out["cpu_baseline"] = cpu_baseline(spec, seed0, args.cpu_seconds, first_counters)
     print(json.dumps(out), flush=True)
 
 

@@ -78,15 +78,26 @@ class Ensemble:
         self.mu = self.sd = None      # input standardisation
         self.ymu = self.ysd = None    # per-output target standardisation
 
-    def _standardise(self, X):
-        return ((X - self.mu) / self.sd).astype(np.float32)
+    @staticmethod
+    def _transform(X):
+        """The 8 features re-expressed without changing their information:
+        (is_SISe, beta/gamma, upsilon/gamma, log gamma, log initial
+        prevalence, mean and variance of log node size, log Nn)."""
+        X = np.asarray(X, dtype=np.float64)
+        g = X[:, 3]
+        return np.stack([X[:, 0], X[:, 1] / g, X[:, 2] / g, np.log(g), np.log(np.maximum(X[:, 4], 1e-12)),
+                         X[:, 5], X[:, 6], X[:, 7]], axis=1)
 
-    def fit(self, X, Y, epochs: int = 60, batch: int = 256, lr: float = 2e-3, weight_decay: float = 1e-4,
+    def _standardise(self, X):
+        return ((self._transform(X) - self.mu) / self.sd).astype(np.float32)
+
+    def fit(self, X, Y, epochs: int = 150, batch: int = 128, lr: float = 4e-3, weight_decay: float = 1e-4,
             seed: int = 0, log=None):
         """Minibatch AdamW on the pinball loss; each member sees its own order."""
         import torch
-        self.mu = X.mean(axis=0)
-        self.sd = X.std(axis=0) + 1e-9
+        Z = self._transform(X)
+        self.mu = Z.mean(axis=0)
+        self.sd = Z.std(axis=0) + 1e-9
         Yf = Y.reshape(len(Y), -1).astype(np.float64)
         # a positive affine map of each output leaves its pinball minimiser
         # (the quantile) equivariant, so the network learns standardised targets
@@ -160,7 +171,7 @@ def choose_threshold(dis, err, eps):
     return float(dis[order[ok[-1]]])
 
 
-def make_dataset(n_train=20000, train_reps=32, n_val=400, val_reps=64, truth_reps=256,
+def make_dataset(n_train=30000, train_reps=32, n_val=1000, val_reps=64, truth_reps=256,
                  nn_range=(100, 20_000), seed=11, log=print):
     """SSA-generated training and held-out data: features X, training targets
     (train_reps-replicate quantiles), held-out ground truth (truth_reps
@@ -181,7 +192,7 @@ def make_dataset(n_train=20000, train_reps=32, n_val=400, val_reps=64, truth_rep
                 nn_range=nn_range, seed=seed)
 
 
-def evaluate(ds=None, members=4, epochs=300, batch=256, lr=2e-3, weight_decay=1e-4, log=print, **data_args):
+def evaluate(ds=None, members=4, epochs=150, batch=128, lr=4e-3, weight_decay=1e-4, log=print, **data_args):
     """The surrogate experiment on a dataset from make_dataset (made here when
     not given): train the ensemble, then on the held-out sets compare (a) the
     val_reps-replicate SSA and (b) the surrogate with SSA fallback, both
@@ -226,3 +237,34 @@ def evaluate(ds=None, members=4, epochs=300, batch=256, lr=2e-3, weight_decay=1e
     res["spearman_dis_err"] = float(np.corrcoef(np.argsort(np.argsort(dis)), np.argsort(np.argsort(err_nn)))[0, 1])
     ens.close()
     return res, dict(pred=pred, dis=dis)
+
+
+def main(argv=None):
+    """python -m paper_1605_01421_amd.surrogate [--n-train N] ... : the whole
+    experiment on cuda:0; progress lines go to stdout, the result is the
+    last line (JSON)."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-train", type=int, default=30000)
+    ap.add_argument("--train-reps", type=int, default=32)
+    ap.add_argument("--n-val", type=int, default=1000)
+    ap.add_argument("--members", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=4e-3)
+    ap.add_argument("--seed", type=int, default=11)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+
+    def log(msg):
+        print(f"[{time.time() - t0:7.1f}s] {msg}", flush=True)
+
+    ds = make_dataset(n_train=args.n_train, train_reps=args.train_reps, n_val=args.n_val, seed=args.seed, log=log)
+    res, _ = evaluate(ds, members=args.members, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    res["wall_s"] = time.time() - t0
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
