@@ -202,7 +202,7 @@ int default_wide(const siminf_model* m, const Group& g, int div = 16) {
 // fit on the device at once, else grid barrier), 1 barrier, 2 dataflow.
 int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode) {
     KParams& p = g.p;
-    const int n = g.n, nc = g.shape.nc;
+    const int n = g.n;
     const int cus = device_cus(m);
     if (cus <= 0) return SIMINF_E_DEVICE;
     nbig = std::max(0, std::min(nbig, n));

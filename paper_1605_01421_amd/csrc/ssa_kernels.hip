@@ -293,9 +293,6 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             // checks of the state: 1 a negative compartment, 2 a bad rate,
             // 4 lambda <= 0 (the node stops for the day)
             const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
-            const int to = (lk + 1) * (lk + 2) / 2 + la + (n == 0 ? 1 : 0);
-            const int chk_to = __shfl(chk, to < WAVE ? to : 0, WAVE);
-            const int word = n | (chk_to << 1);
             // the window's first state (the day's starting state or the one
             // the previous window ended in) is checked before its draw
             const int c00 = __builtin_amdgcn_readfirstlane(chk);
@@ -309,34 +306,69 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
                 done = true;
                 break;
             }
-            // the walk: k steps taken, a of them of the first kind
-            int a = 0, k = 0, fail = 0;
-            bool boundary = false;
-            for (; k < wlen; ++k) {
-                const int L = k * (k + 1) / 2 + a;
-                ++nd;
-                const double tn = t + read_lane(tau, L);
-                if (tn >= T) {
-                    boundary = true;
-                    break;
+            // The path does not depend on t: bit L of `first` says whether the
+            // step from point L is of the first kind, and point (k+1, a') is
+            // L + k + 1 + d.  Lane k records the point and a of step k, and
+            // the point the step leads to.
+            const unsigned long long first = __ballot(n == 0);
+            int pidx = 0, pa = 0, pnext = 0;
+            int L = 0, a = 0;
+#pragma unroll
+            for (int k = 0; k < LAT_W; ++k) {
+                if (k < wlen) {
+                    pidx = lane == k ? L : pidx;
+                    pa = lane == k ? a : pa;
+                    const int d = (int)((first >> L) & 1ull);
+                    a += d;
+                    L += k + 1 + d;
+                    pnext = lane == k ? L : pnext;
                 }
-                t = tn;
-                const int w = __builtin_amdgcn_readlane(word, L);
-                a += (w & 1) ? 0 : 1;
-                ++ntr;
-                if (k + 1 < wlen && (w >> 1)) {
-                    fail = w >> 1;
-                    ++k;
-                    break;
+            }
+            const double tp = __shfl(tau, pidx, WAVE);
+            const int chk_next = __shfl(chk, pnext < WAVE ? pnext : 0, WAVE);
+            // the time chain, the one serial part: lane k keeps the time
+            // before step k; t + tau of each step is one addition, in order
+            double tl = t;
+#pragma unroll
+            for (int k = 0; k < LAT_W; ++k) {
+                if (k < wlen) {
+                    tl = lane == k ? t : tl;
+                    t = t + read_lane(tp, k);
                 }
+            }
+            // first step whose draw would cross the boundary, and first step
+            // whose transition leads to a state that fails its checks (the
+            // last step's successor is checked by the next window)
+            const unsigned long long cross = __ballot(lane < wlen && tl + tp >= T);
+            const unsigned long long fail = __ballot(lane + 1 < wlen && chk_next != 0);
+            const int kc = cross ? __builtin_ctzll(cross) : WAVE;
+            const int kf = fail ? __builtin_ctzll(fail) : WAVE;
+            int kend, aend;
+            if (kc <= kf && kc < wlen) {
+                // stops at the boundary before the transition of step kc
+                kend = kc;
+                aend = __builtin_amdgcn_readlane(pa, kc);
+                nd += (uint32_t)kc + 1u;
+                ntr += (uint32_t)kc;
+                done = true;
+            } else if (kf < wlen) {
+                // the transition of step kf leads to a failing state
+                kend = kf + 1;
+                aend = __builtin_amdgcn_readlane(pa, kf + 1);
+                const int code = __builtin_amdgcn_readlane(chk_next, kf);
+                rc = (code & 1) ? E_NEG_STATE : (code & 2) ? E_BAD_RATE : 0;
+                nd += (uint32_t)kf + 1u;
+                ntr += (uint32_t)kf + 1u;
+                done = true;
+            } else {
+                kend = wlen;
+                aend = a;
+                nd += (uint32_t)wlen;
+                ntr += (uint32_t)wlen;
             }
 #pragma unroll
-            for (int c = 0; c < M::NC; ++c) s.u[c] += a * S0[c] + (k - a) * S1[c];
-            if (boundary || fail) {
-                rc = (fail & 1) ? E_NEG_STATE : (fail & 2) ? E_BAD_RATE : 0;
-                done = true;
-                break;
-            }
+            for (int c = 0; c < M::NC; ++c) s.u[c] += aend * S0[c] + (kend - aend) * S1[c];
+            if (done) break;
         }
     }
     if (lane == 0) {
