@@ -60,6 +60,17 @@ struct EventSoA {
     const int32_t* run;      // E2: run of the event (its sampling stream is stream_base + run)
 };
 
+// Position of record m, component c (of width components) of node k in a
+// trajectory buffer of ntspan records of n nodes.  The first nbig nodes, each
+// carried by a whole wavefront, are stored node-major so that one node's
+// consecutive records fill the same cache lines from one wavefront; the
+// others are stored component-major per record, so that the 64 nodes of a
+// wavefront store contiguous runs.
+__host__ __device__ inline size_t rec_index(int m, int c, int k, int width, int ntspan, int n, int nbig) {
+    if (k < nbig) return ((size_t)k * ntspan + m) * width + c;
+    return (size_t)nbig * ntspan * width + ((size_t)m * width + c) * (size_t)(n - nbig) + (size_t)(k - nbig);
+}
+
 struct KParams {
     int32_t n;        // nodes in the group
     int32_t nb;       // number of unit-time steps
@@ -117,7 +128,7 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem,
                         hipStream_t st);
 int max_blocks_per_cu(int model, int mode, int pipeline, int block, size_t shmem);
-hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan,
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nbig,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
 hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,
                              int case_c, uint32_t mask, int reps, int k0, int nk,

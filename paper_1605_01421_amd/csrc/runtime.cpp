@@ -871,7 +871,7 @@ int siminf_trajectory(siminf_model* m, int32_t run, int32_t* U, double* V, int32
         } else tmpV = true;
     }
     int rc = SIMINF_OK;
-    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, m->d_pos + ri.noff, ri.nn, dU, dV, nullptr) !=
+    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, g.p.nbig, m->d_pos + ri.noff, ri.nn, dU, dV, nullptr) !=
             hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         rc = SIMINF_E_DEVICE;

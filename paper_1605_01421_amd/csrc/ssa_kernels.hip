@@ -458,9 +458,9 @@ __device__ __forceinline__ void record(const KParams& p, const Node<M>& s, int k
         if (p.record == 0) {
             if (active) {
 #pragma unroll
-                for (int c = 0; c < M::NC; ++c) p.U[((size_t)m * M::NC + c) * p.n + k] = s.u[c];
+                for (int c = 0; c < M::NC; ++c) p.U[rec_index(m, c, k, M::NC, p.ntspan, p.n, p.nbig)] = s.u[c];
 #pragma unroll
-                for (int c = 0; c < M::NV; ++c) p.V[((size_t)m * M::NV + c) * p.n + k] = s.v[c];
+                for (int c = 0; c < M::NV; ++c) p.V[rec_index(m, c, k, M::NV, p.ntspan, p.n, p.nbig)] = s.v[c];
             }
         } else {
             const int lane = threadIdx.x & (WAVE - 1);
@@ -906,15 +906,15 @@ __global__ void init_kernel(KParams p, int nc, int nv, int first_rec, int reset_
         if (p.record == 0) {
             for (int m = 0; m < first_rec; ++m) {
                 for (int c = 0; c < nc; ++c)
-                    p.U[((size_t)m * nc + c) * p.n + k] = p.u0[(size_t)c * p.n + k];
+                    p.U[rec_index(m, c, k, nc, p.ntspan, p.n, p.nbig)] = p.u0[(size_t)c * p.n + k];
                 for (int c = 0; c < nv; ++c)
-                    p.V[((size_t)m * nv + c) * p.n + k] = p.v0[(size_t)c * p.n + k];
+                    p.V[rec_index(m, c, k, nv, p.ntspan, p.n, p.nbig)] = p.v0[(size_t)c * p.n + k];
             }
         }
     }
 }
 
-__global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv, int n, int ntspan,
+__global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv, int n, int ntspan, int nbig,
                               const int32_t* pos, int nn, int32_t* Uo, double* Vo) {
     const long long total = (long long)ntspan * nn;
     for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
@@ -922,9 +922,9 @@ __global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv,
         const int m = (int)(idx / nn), i = (int)(idx % nn);
         const int k = pos[i];
         if (Uo)
-            for (int c = 0; c < nc; ++c) Uo[((size_t)m * nn + i) * nc + c] = U[((size_t)m * nc + c) * n + k];
+            for (int c = 0; c < nc; ++c) Uo[((size_t)m * nn + i) * nc + c] = U[rec_index(m, c, k, nc, ntspan, n, nbig)];
         if (Vo)
-            for (int c = 0; c < nv; ++c) Vo[((size_t)m * nn + i) * nv + c] = V[((size_t)m * nv + c) * n + k];
+            for (int c = 0; c < nv; ++c) Vo[((size_t)m * nn + i) * nv + c] = V[rec_index(m, c, k, nv, ntspan, n, nbig)];
     }
 }
 
@@ -1014,11 +1014,11 @@ int max_blocks_per_cu(int model, int mode, int pipeline, int block, size_t shmem
     return n;
 }
 
-hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, const int32_t* pos,
-                         int nn, int32_t* Uo, double* Vo, hipStream_t st) {
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nbig,
+                         const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st) {
     long long total = (long long)ntspan * nn;
     int blocks = (int)std::max<long long>(1, std::min<long long>((total + 255) / 256, 8192));
-    gather_kernel<<<blocks, 256, 0, st>>>(U, V, nc, nv, n, ntspan, pos, nn, Uo, Vo);
+    gather_kernel<<<blocks, 256, 0, st>>>(U, V, nc, nv, n, ntspan, nbig, pos, nn, Uo, Vo);
     return hipGetLastError();
 }
 
