@@ -143,6 +143,67 @@ def cpu_baseline(spec, seed, seconds, gpu_counters):
                       f"{t_total:.1f} s of CPU time", "counters_match_gpu": parity}
 
 
+MLP_DIMS = (8, 256, 256, 256, 256, 156)
+BF16_PEAK = 2.5e15  # dense bf16 matrix-core FLOP/s of the MI355X (published)
+
+
+def bench_mlp(args):
+    """The surrogate network on the matrix cores: K training steps (forward,
+    backward and AdamW at batch 4096) and K inference passes at batch 65536,
+    each timed with HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    from paper_1605_01421_amd import siminf
+    from paper_1605_01421_amd import workloads as W
+    torch.cuda.set_device(0)
+    fwd_flops = 2 * sum(a * b for a, b in zip(MLP_DIMS[:-1], MLP_DIMS[1:]))
+    # backward: the weight gradient of every layer and the input gradient of
+    # every layer but the first
+    bwd_flops = 2 * fwd_flops - 2 * MLP_DIMS[0] * MLP_DIMS[1]
+    rng = np.random.default_rng(0)
+    Bt, Bi = 4096, 65536
+    net = siminf.MLP(MLP_DIMS, Bi)
+    net.set_params(W.mlp_init(MLP_DIMS, 1))
+    Xt = torch.from_numpy(rng.normal(size=(Bt, 8)).astype(np.float32)).cuda()
+    Tt = torch.from_numpy(rng.normal(size=(Bt, 156)).astype(np.float32)).cuda()
+    Xi = torch.from_numpy(rng.normal(size=(Bi, 8)).astype(np.float32)).cuda()
+    Yi = torch.empty((Bi, 156), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        net.backward(Xt, Tt, want_loss=False)
+        net.adamw(1e-4)
+        net.forward(Xi, Yi)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(args.steps):
+        net.backward(Xt, Tt, want_loss=False)
+        net.adamw(1e-4)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(args.steps):
+        net.forward(Xi, Yi)
+    ev[3].record()
+    torch.cuda.synchronize()
+    t_train = ev[0].elapsed_time(ev[1]) / 1e3 / args.steps
+    t_inf = ev[2].elapsed_time(ev[3]) / 1e3 / args.steps
+    inf_achieved = fwd_flops * Bi / t_inf
+    out = {
+        "metric": "surrogate MLP training samples/s (batch 4096, forward + backward + AdamW)",
+        "value": Bt / t_train, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_train * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "surrogate-mlp", "dims": list(MLP_DIMS), "train_batch": Bt, "infer_batch": Bi},
+        "train_tflops": (fwd_flops + bwd_flops) * Bt / t_train / 1e12,
+        "inference_samples_per_s": Bi / t_inf, "inference_ms": t_inf * 1e3,
+        "roofline": {"bound": "mfma", "achieved": inf_achieved / 1e12, "peak": BF16_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": inf_achieved / BF16_PEAK, "traffic": None,
+                     "kernel": "forward pass at batch 65536 (five bf16 GEMMs with fused epilogues)",
+                     "flops_per_sample": fwd_flops},
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +231,9 @@ def main():
     from paper_1605_01421_amd import siminf
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "mlp":
+        bench_mlp(args)
+        return
     torch.cuda.set_device(0)
     spec, desc = build_workload(args.workload)
     batch = isinstance(spec, list)

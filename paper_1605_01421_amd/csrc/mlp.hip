@@ -21,9 +21,9 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TILE = 64;  // output tile per workgroup (M and N)
-constexpr int KT = 32;    // K per matrix-core step
-constexpr int LDS_K = 40; // padded row length of the LDS tiles (bf16 elements)
+constexpr int BM = 128, BN = 128;  // output tile per workgroup of 256 threads
+constexpr int KT = 32;             // K per matrix-core step
+constexpr int LDS_K = 40;          // padded LDS row (bf16 elements): 80 B, 16-byte aligned
 
 __host__ __device__ inline uint16_t f32_to_bf16(float f) {
     uint32_t u;
@@ -45,7 +45,9 @@ __device__ inline float gelu_grad(float z) {
     return 0.5f * erfcf(-z * 0.70710678118654752f) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2 };
+// Epilogues: float32 result (+ bias); GELU with the pre-activation kept
+// (training) or not (inference); gradient times GELU'; split-K partial.
+enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_DGELU = 2, EPI_GELU_ACT = 3, EPI_PART = 4 };
 
 struct GemmArgs {
     int M, N, K;
@@ -54,95 +56,170 @@ struct GemmArgs {
     const uint16_t* B;
     int ldb;  // BT ? B[k*ldb + n] : B[n*ldb + k]
     const float* bias;  // [N] or null
-    float* Cf;          // float32 result (EPI_STORE, EPI_GELU pre-activation)
+    float* Cf;          // float32 result (EPI_STORE, EPI_GELU pre-activation, EPI_PART partials)
     int ldc;
-    uint16_t* Cb;  // bfloat16 result (EPI_GELU activation, EPI_DGELU gradient)
+    uint16_t* Cb;  // bfloat16 result (EPI_GELU / EPI_GELU_ACT activation, EPI_DGELU gradient)
     int ldcb;
     const float* Zp;  // EPI_DGELU: pre-activations the gradient is multiplied by GELU' of
     int ldzp;
+    int kslice;  // K range of one blockIdx.z (a multiple of KT)
 };
 
-// C[M,N] = A[M,K] B[K,N] + bias, one 64x64 tile per workgroup of 256 threads.
-// Wavefront w computes rows 32*(w/2).., columns 32*(w%2).. as 2x2 tiles of
-// 16x16.  Operand tiles are staged in LDS as [row][k] so every lane reads its
-// eight consecutive k values (lane l: row l%16, k 8*(l/16)..+7) in one load,
-// whatever the orientation of the operand in global memory.
-template <bool AT, bool BT, int EPI>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[TILE * LDS_K];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[TILE * LDS_K];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+// Global -> register staging of one operand tile of R rows x KT k values.
+// The operand is stored [row][k] (TRANS false, rows ld apart) or [k][row]
+// (TRANS true); either way the LDS tile is [row][k], so that every lane
+// reads the eight consecutive k values of its matrix-core operand in one
+// 16-byte load.  VEC elements move per global load (8, 4 or 1): whole
+// vectors inside the matrix, element by element at its ragged edges.
+template <bool TRANS, int VEC, int R>
+struct Stage {
+    static constexpr int NV = R * KT / VEC / 256;
+    static constexpr int NW = VEC > 1 ? VEC / 2 : 1;  // 32-bit words per vector
+    static_assert(NV * VEC * 256 == R * KT, "tile does not split evenly over the workgroup");
+    uint32_t w[NV][NW];
 
-    for (int k0 = 0; k0 < g.K; k0 += KT) {
-        // ---- stage A (64 rows x 32 k) and B (64 cols x 32 k) in LDS
-        if (!AT) {
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            const int gm = m0 + r, gk = k0 + kc;
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                As[r * LDS_K + kc + i] = (gm < g.M && gk + i < g.K) ? g.A[(size_t)gm * g.lda + gk + i] : 0;
+    __device__ __forceinline__ static void where(int i, int& row, int& k) {
+        if (!TRANS) {
+            row = i / (KT / VEC);
+            k = (i % (KT / VEC)) * VEC;
         } else {
-            const int kk = tid >> 3, mc = (tid & 7) * 8;
-            const int gk = k0 + kk;
+            k = i / (R / VEC);
+            row = (i % (R / VEC)) * VEC;
+        }
+    }
+
+    __device__ __forceinline__ static uint16_t half(const uint32_t (&x)[NW], int e) {
+        if constexpr (VEC == 1) return (uint16_t)x[0];
+        else return (uint16_t)(x[e >> 1] >> (16 * (e & 1)));
+    }
+
+    __device__ __forceinline__ void load(const uint16_t* P, int ld, int rows, int kend, int r0, int k0, int tid) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gm = m0 + mc + i;
-                As[(mc + i) * LDS_K + kk] = (gm < g.M && gk < g.K) ? g.A[(size_t)gk * g.lda + gm] : 0;
+        for (int j = 0; j < NV; ++j) {
+            int row, k;
+            where(tid + j * 256, row, k);
+            const int gr = r0 + row, gk = k0 + k;
+            const bool full = !TRANS ? (gr < rows && gk + VEC <= kend) : (gk < kend && gr + VEC <= rows);
+            const uint16_t* q = P + (!TRANS ? (size_t)gr * ld + gk : (size_t)gk * ld + gr);
+            if (full) {
+                if constexpr (VEC == 8) {
+                    const uint4 x = *reinterpret_cast<const uint4*>(q);
+                    w[j][0] = x.x;
+                    w[j][1] = x.y;
+                    w[j][2] = x.z;
+                    w[j][3] = x.w;
+                } else if constexpr (VEC == 4) {
+                    const uint2 x = *reinterpret_cast<const uint2*>(q);
+                    w[j][0] = x.x;
+                    w[j][1] = x.y;
+                } else {
+                    w[j][0] = q[0];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NW; ++e) w[j][e] = 0u;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool in = !TRANS ? (gr < rows && gk + e < kend) : (gk < kend && gr + e < rows);
+                    const uint32_t h = in ? (uint32_t)q[e] : 0u;
+                    if constexpr (VEC == 1) w[j][0] = h;
+                    else w[j][e >> 1] |= h << (16 * (e & 1));
+                }
             }
         }
-        if (!BT) {
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            const int gn = n0 + r, gk = k0 + kc;
+    }
+
+    __device__ __forceinline__ void store(uint16_t* S, int tid) const {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                Bs[r * LDS_K + kc + i] = (gn < g.N && gk + i < g.K) ? g.B[(size_t)gn * g.ldb + gk + i] : 0;
-        } else {
-            const int kk = tid >> 3, nc = (tid & 7) * 8;
-            const int gk = k0 + kk;
+        for (int j = 0; j < NV; ++j) {
+            int row, k;
+            where(tid + j * 256, row, k);
+            if (!TRANS) {
+                if constexpr (VEC == 8) {
+                    *reinterpret_cast<uint4*>(&S[row * LDS_K + k]) = uint4{w[j][0], w[j][1], w[j][2], w[j][3]};
+                } else if constexpr (VEC == 4) {
+                    *reinterpret_cast<uint2*>(&S[row * LDS_K + k]) = uint2{w[j][0], w[j][1]};
+                } else {
+                    S[row * LDS_K + k] = (uint16_t)w[j][0];
+                }
+            } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int gn = n0 + nc + i;
-                Bs[(nc + i) * LDS_K + kk] = (gn < g.N && gk < g.K) ? g.B[(size_t)gk * g.ldb + gn] : 0;
+                for (int e = 0; e < VEC; ++e) S[(row + e) * LDS_K + k] = half(w[j], e);
             }
         }
+    }
+};
+
+// C[M,N] = A[M,K] B[K,N] (+ bias): a 128x128 tile per workgroup of four
+// wavefronts, each computing 64x64 as 4x4 matrix-core tiles of 16x16 with
+// K = 32 per step.  The next K step's operands are loaded from global memory
+// into registers while the current step runs on the matrix cores.  With
+// EPI_PART, blockIdx.z computes the partial product over its K slice.
+template <bool AT, bool BT, int EPI, int VEC>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDS_K];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDS_K];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int kbeg = blockIdx.z * g.kslice;
+    const int kend = min(g.K, kbeg + g.kslice);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    Stage<AT, VEC, BM> sa;
+    Stage<BT, VEC, BN> sb;
+    if (kbeg < kend) {
+        sa.load(g.A, g.lda, g.M, kend, m0, kbeg, tid);
+        sb.load(g.B, g.ldb, g.N, kend, n0, kbeg, tid);
+    }
+    const int kq = (lane >> 4) * 8, rl = lane & 15;
+    for (int k0 = kbeg; k0 < kend; k0 += KT) {
+        sa.store(As, tid);
+        sb.store(Bs, tid);
         __syncthreads();
-        // ---- 2x2 matrix-core products per wavefront
-        bf16x8 a[2], b[2];
-        const int kq = (lane >> 4) * 8, rl = lane & 15;
+        if (k0 + KT < kend) {
+            sa.load(g.A, g.lda, g.M, kend, m0, k0 + KT, tid);
+            sb.load(g.B, g.ldb, g.N, kend, n0, k0 + KT, tid);
+        }
+        bf16x8 a[4], b[4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < 4; ++i) {
             a[i] = *reinterpret_cast<const bf16x8*>(&As[(wr + i * 16 + rl) * LDS_K + kq]);
             b[i] = *reinterpret_cast<const bf16x8*>(&Bs[(wc + i * 16 + rl) * LDS_K + kq]);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
     // ---- epilogue: lane l holds rows 4*(l/16)+r, column l%16 of each 16x16 tile
+    float* part = EPI == EPI_PART ? g.Cf + (size_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + r;
                 const int n = n0 + wc + j * 16 + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][j][r];
+                if (EPI == EPI_PART) {
+                    part[(size_t)m * g.N + n] = v;
+                    continue;
+                }
                 if (g.bias) v += g.bias[n];
                 if (EPI == EPI_STORE) {
                     g.Cf[(size_t)m * g.ldc + n] = v;
                 } else if (EPI == EPI_GELU) {
                     g.Cf[(size_t)m * g.ldc + n] = v;
+                    g.Cb[(size_t)m * g.ldcb + n] = f32_to_bf16(gelu(v));
+                } else if (EPI == EPI_GELU_ACT) {
                     g.Cb[(size_t)m * g.ldcb + n] = f32_to_bf16(gelu(v));
                 } else {
                     g.Cb[(size_t)m * g.ldcb + n] = f32_to_bf16(v * gelu_grad(g.Zp[(size_t)m * g.ldzp + n]));
@@ -150,11 +227,57 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
             }
 }
 
+// C[m,n] = sum over s of the split-K partials P[s][m][n], in slice order.
+__global__ void splitk_reduce_kernel(const float* P, int S, int M, int N, float* C, int ldc) {
+    const long long total = (long long)M * N;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < S; ++z) s += P[(size_t)z * total + i];
+        C[(i / N) * ldc + (i % N)] = s;
+    }
+}
+
+// Widest vector both operands allow: row stride and base address aligned.
+inline int vec_width(const GemmArgs& g) {
+    auto ok = [&](int v) {
+        return g.lda % v == 0 && g.ldb % v == 0 && ((uintptr_t)g.A % (2 * v)) == 0 && ((uintptr_t)g.B % (2 * v)) == 0;
+    };
+    return ok(8) ? 8 : ok(4) ? 4 : 1;
+}
+
 template <bool AT, bool BT, int EPI>
-hipError_t gemm(const GemmArgs& g, hipStream_t st) {
+hipError_t gemm(GemmArgs g, hipStream_t st, float* work = nullptr, int max_slices = 1) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE);
-    gemm_kernel<AT, BT, EPI><<<grid, 256, 0, st>>>(g);
+    const int tiles = ((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM);
+    // split K when the output has few tiles and K is long (weight gradients)
+    int S = 1;
+    if (EPI == EPI_STORE && work && g.bias == nullptr)
+        S = std::max(1, std::min({max_slices, (g.K + 255) / 256, std::max(1, 256 / std::max(tiles, 1))}));
+    const int steps = (g.K + KT - 1) / KT;
+    g.kslice = ((steps + S - 1) / S) * KT;
+    if (g.kslice <= 0) g.kslice = KT;
+    S = std::max(1, (g.K + g.kslice - 1) / g.kslice);
+    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, S);
+    const int vec = vec_width(g);
+    GemmArgs pg = g;
+    if (S > 1) pg.Cf = work;
+#define SIMINF_GEMM_LAUNCH(E)                                                              \
+    do {                                                                                   \
+        if (vec == 8) gemm_kernel<AT, BT, E, 8><<<grid, 256, 0, st>>>(pg);                 \
+        else if (vec == 4) gemm_kernel<AT, BT, E, 4><<<grid, 256, 0, st>>>(pg);            \
+        else gemm_kernel<AT, BT, E, 1><<<grid, 256, 0, st>>>(pg);                          \
+    } while (0)
+    if (S > 1) {
+        SIMINF_GEMM_LAUNCH(EPI_PART);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+        const long long total = (long long)g.M * g.N;
+        const int blocks = (int)std::max<long long>(1, std::min<long long>((total + 255) / 256, 4096));
+        splitk_reduce_kernel<<<blocks, 256, 0, st>>>(work, S, g.M, g.N, g.Cf, g.ldc);
+    } else {
+        SIMINF_GEMM_LAUNCH(EPI);
+    }
+#undef SIMINF_GEMM_LAUNCH
     return hipGetLastError();
 }
 
@@ -171,28 +294,47 @@ struct Levels {
 __global__ void zero_kernel(double* x) { *x = 0.0; }
 
 // Pinball loss (sum accumulated in *loss) and its gradient dY / (B*N) as bf16.
-__global__ void pinball_kernel(const float* Y, const float* T, int B, int N, Levels lv, uint16_t* dY,
-                               double* loss) {
-    const long long total = (long long)B * N;
+__global__ void __launch_bounds__(256) pinball_kernel(const float* Y, const float* T, int B, int N, Levels lv,
+                                                      uint16_t* dY, double* loss) {
+    __shared__ double red[4];
+    const int total = B * N;
     double part = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int j = (int)(i % N);
-        const float q = lv.q[j % lv.nq];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int r = (i % N) % lv.nq;
+        float q = lv.q[0];
+#pragma unroll
+        for (int c = 1; c < 8; ++c) q = r == c ? lv.q[c] : q;  // selects: no indexed private array
         const float d = T[i] - Y[i];
         part += d > 0.f ? (double)q * d : (double)(q - 1.f) * d;
         dY[i] = f32_to_bf16((d > 0.f ? -q : 1.f - q) / (float)total);
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, ((red[0] + red[1]) + red[2]) + red[3]);
 }
 
-// db[n] = sum_b dZ[b, n]
-__global__ void colsum_kernel(const uint16_t* dZ, int B, int N, float* db) {
+// Column sums db[n] = sum_b dZ[b, n] in two deterministic passes: block
+// (x, y) sums rows 256y.. of columns 64x.. (64 columns x 4 row lanes, then
+// an LDS reduction) into part[y][n]; colsum_finish adds the parts in order.
+__global__ void colsum_kernel(const uint16_t* dZ, int B, int N, int ld, float* part) {
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, rlane = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    const int r0 = blockIdx.y * 256;
+    float s = 0.f;
+    if (n < N)
+        for (int r = r0 + rlane; r < min(B, r0 + 256); r += 4) s += bf16_to_f32(dZ[(size_t)r * ld + n]);
+    red[rlane][c] = s;
+    __syncthreads();
+    if (rlane == 0 && n < N) part[(size_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void colsum_finish(const float* part, int chunks, int N, float* db) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += bf16_to_f32(dZ[(size_t)b * N + n]);
+    for (int y = 0; y < chunks; ++y) s += part[(size_t)y * N + n];
     db[n] = s;
 }
 
@@ -224,7 +366,11 @@ struct siminf_mlp {
     std::vector<uint16_t*> Wb, A, dZ;
     double* loss = nullptr;
     float* Y = nullptr;
+    float* work = nullptr;   // split-K partial products of the weight gradients
+    float* cpart = nullptr;  // column-sum partials of the bias gradients
 };
+
+constexpr int MAX_SLICES = 16;  // split-K slices of a weight-gradient product
 
 namespace {
 template <class T>
@@ -235,7 +381,8 @@ bool dalloc(siminf_mlp* m, size_t n, T** p) {
     return hipMemset(*p, 0, sizeof(T) * std::max<size_t>(n, 1)) == hipSuccess;
 }
 
-int mlp_forward(siminf_mlp* m, const float* X, int B, hipStream_t st) {
+// train: keep the float32 pre-activations that the backward pass needs.
+int mlp_forward(siminf_mlp* m, const float* X, int B, hipStream_t st, bool train) {
     const long long nin = (long long)B * m->dims[0];
     to_bf16_kernel<<<grid_for(nin), 256, 0, st>>>(X, m->A[0], nin);
     if (hipGetLastError() != hipSuccess) return SIMINF_E_DEVICE;
@@ -255,7 +402,7 @@ int mlp_forward(siminf_mlp* m, const float* X, int B, hipStream_t st) {
         if (l + 1 < m->L) {
             g.Cb = m->A[l + 1];
             g.ldcb = g.N;
-            e = gemm<false, false, EPI_GELU>(g, st);
+            e = train ? gemm<false, false, EPI_GELU>(g, st) : gemm<false, false, EPI_GELU_ACT>(g, st);
         } else {
             e = gemm<false, false, EPI_STORE>(g, st);
         }
@@ -270,7 +417,7 @@ extern "C" {
 int siminf_mlp_create(int32_t nlayers, const int32_t* dims, int32_t max_batch, siminf_mlp** out) {
     if (!out || !dims || nlayers < 1 || nlayers > 64 || max_batch < 1) return SIMINF_E_ARG;
     for (int i = 0; i <= nlayers; ++i)
-        if (dims[i] < 1 || dims[i] > 65536) return SIMINF_E_ARG;
+        if (dims[i] < 1 || dims[i] > 65536 || (long long)dims[i] * max_batch > 0x7FFFFFFFLL) return SIMINF_E_ARG;
     siminf_mlp* m = new (std::nothrow) siminf_mlp();
     if (!m) return SIMINF_E_ALLOC;
     *out = m;
@@ -298,7 +445,13 @@ int siminf_mlp_create(int32_t nlayers, const int32_t* dims, int32_t max_batch, s
              dalloc(m, nw, &m->Wb[l]) && dalloc(m, nz, &m->dZ[l]) &&
              dalloc(m, (size_t)max_batch * dims[l], &m->A[l]);
     }
-    ok = ok && dalloc(m, 1, &m->loss);
+    size_t wmax = 1, nmax = 1;
+    for (int l = 0; l < nlayers; ++l) {
+        wmax = std::max(wmax, (size_t)dims[l + 1] * dims[l]);
+        nmax = std::max(nmax, (size_t)dims[l + 1]);
+    }
+    ok = ok && dalloc(m, 1, &m->loss) && dalloc(m, (size_t)MAX_SLICES * wmax, &m->work) &&
+         dalloc(m, (size_t)((max_batch + 255) / 256) * nmax, &m->cpart);
     if (!ok) return SIMINF_E_ALLOC;
     return SIMINF_OK;
 }
@@ -340,7 +493,7 @@ int siminf_mlp_get_grads(const siminf_mlp* m, int32_t layer, float* dW, float* d
 int siminf_mlp_forward(siminf_mlp* m, const float* X, int32_t B, float* Y, void* hip_stream) {
     if (!m || !X || !Y || B < 1 || B > m->max_batch) return SIMINF_E_ARG;
     hipStream_t st = (hipStream_t)hip_stream;
-    const int rc = mlp_forward(m, X, B, st);
+    const int rc = mlp_forward(m, X, B, st, false);
     if (rc) return rc;
     const size_t ny = (size_t)B * m->dims[m->L];
     return hipMemcpyAsync(Y, m->Z[m->L - 1], ny * 4, hipMemcpyDeviceToDevice, st) == hipSuccess ? SIMINF_OK
@@ -355,10 +508,10 @@ int siminf_mlp_backward(siminf_mlp* m, const float* X, const float* T, int32_t B
     lv.nq = nq;
     for (int i = 0; i < nq; ++i) lv.q[i] = (float)probs[i];
     zero_kernel<<<1, 1, 0, st>>>(m->loss);
-    int rc = mlp_forward(m, X, B, st);
+    int rc = mlp_forward(m, X, B, st, true);
     if (rc) return rc;
     const int L = m->L, Nout = m->dims[L];
-    pinball_kernel<<<grid_for((long long)B * Nout), 256, 0, st>>>(m->Z[L - 1], T, B, Nout, lv, m->dZ[L - 1],
+    pinball_kernel<<<std::min(grid_for((long long)B * Nout), 512), 256, 0, st>>>(m->Z[L - 1], T, B, Nout, lv, m->dZ[L - 1],
                                                                  m->loss);
     if (hipGetLastError() != hipSuccess) return SIMINF_E_DEVICE;
     for (int l = L - 1; l >= 0; --l) {
@@ -374,8 +527,10 @@ int siminf_mlp_backward(siminf_mlp* m, const float* X, const float* T, int32_t B
         g.ldb = K;
         g.Cf = m->gW[l];
         g.ldc = K;
-        if (gemm<true, true, EPI_STORE>(g, st) != hipSuccess) return SIMINF_E_DEVICE;
-        colsum_kernel<<<(N + 255) / 256, 256, 0, st>>>(m->dZ[l], B, N, m->gb[l]);
+        if (gemm<true, true, EPI_STORE>(g, st, m->work, MAX_SLICES) != hipSuccess) return SIMINF_E_DEVICE;
+        const int chunks = (B + 255) / 256;
+        colsum_kernel<<<dim3((N + 63) / 64, chunks), 256, 0, st>>>(m->dZ[l], B, N, N, m->cpart);
+        colsum_finish<<<(N + 255) / 256, 256, 0, st>>>(m->cpart, chunks, N, m->gb[l]);
         if (hipGetLastError() != hipSuccess) return SIMINF_E_DEVICE;
         if (l > 0) {
             // dZ_{l-1}[B,K] = (dZ_l W_l) * GELU'(Z_{l-1})

@@ -35,11 +35,14 @@ def _bf16_bits(x):
     return t.view(torch.int16).cuda(), t.to(torch.float64).numpy()
 
 
+@pytest.mark.parametrize("shape", [(70, 130, 45), (300, 264, 264), (129, 8, 256), (513, 160, 8)])
 @pytest.mark.parametrize("a_trans,b_trans", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_gemm_orientations(lib, a_trans, b_trans):
+def test_gemm_orientations(lib, a_trans, b_trans, shape):
+    """Odd leading dimensions take element loads; multiples of 8 take
+    16-byte vector loads; tile edges are ragged in M, N and K."""
     import torch
     rng = np.random.default_rng(a_trans * 2 + b_trans)
-    M, N, K = 70, 130, 45
+    M, N, K = shape
     A = rng.normal(size=(M, K))
     B = rng.normal(size=(K, N))
     Astore = A.T if a_trans else A          # a_trans: stored K x M
@@ -78,9 +81,11 @@ def test_forward_matches_oracle(lib):
     assert _relf(Y, want) < 5e-3
 
 
-def test_gradients_match_oracle(lib):
-    params, rparams, X, T, Xt, Tt = _setup(2, 257)
-    net = lib.MLP(DIMS, 512)
+@pytest.mark.parametrize("B", [257, 3000])
+def test_gradients_match_oracle(lib, B):
+    """B = 3000 splits every weight-gradient product over several K slices."""
+    params, rparams, X, T, Xt, Tt = _setup(2, B)
+    net = lib.MLP(DIMS, 4096)
     net.set_params(params)
     loss = net.backward(Xt, Tt, PROBS)
     wl, wgrads, _ = ref.loss_and_grads(rparams, X, T, PROBS, round_bf16=True)
