@@ -213,10 +213,11 @@ int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32
 int siminf_launch_info(const siminf_model *m, int32_t out[6]);
 
 /* Autotuner: runs the model `repeats` times for each candidate launch shape
- * (threads per block 64/128/256; none, half, the default or twice the
- * default number of wavefront-wide nodes; pipelining on/off), on hip_stream
- * with seeds seed, seed+1, ..., and keeps the shape with the smallest median
- * SSA-kernel time (written to *best_ms if not NULL).  Every shape gives
+ * (threads per block 64/128/256; no wavefront-wide nodes, or those whose
+ * expected work exceeds 1/4, 1/16 or 1/64 of the heaviest node's;
+ * pipelining on/off), on hip_stream with seeds seed, seed+1, ..., and keeps
+ * the shape with the smallest lower-median SSA-kernel time (the faster of
+ * two repeats; written to *best_ms if not NULL).  Every shape gives
  * bit-identical results; the handle's recorded results are overwritten. */
 int siminf_autotune(siminf_model *m, uint64_t seed, int32_t repeats, void *hip_stream, double *best_ms);
 

@@ -120,7 +120,7 @@ def test_other_models(lib, kind):
                                   dict(lanes=1), dict(lanes=64, wide=1), dict(lanes=64, wide=40),
                                   dict(lanes=64, wide=600, block=256), dict(lanes=64, wide=7, block=128, pipeline=2),
                                   dict(lanes=64, wide=600, lattice=2), dict(lanes=64, wide=600, mode=1, lattice=1),
-                                  dict(lanes=64, wide=90, block=64, lattice=2)])
+                                  dict(lanes=64, wide=90, block=64, lattice=2), dict(pipeline=2, block=128)])
 def test_launch_shape_does_not_change_bits(lib, opts):
     spec = W.config1(seed=11, Nn=600, days=50)
     ref = oracle_run(spec, 5, 0)
@@ -303,3 +303,49 @@ def test_wide_node_paths(lib, case, lattice):
     _compare(m, ref, what=case)
     c = m.counters()
     assert (c["transitions"], c["node_days"]) == (ref["transitions"], ref["node_days"])
+
+
+def _no_transfers(spec):
+    ev = {k: np.asarray(v)[np.asarray(spec.events["event"]) != W.EXTTRANS] for k, v in spec.events.items()}
+    return W.sir_spec(np.asarray(spec.u0), np.asarray(spec.tspan), 0.16, 0.077, events=ev, name="no-transfers")
+
+
+@pytest.mark.parametrize("pipeline", [1, 2])
+@pytest.mark.parametrize("case", ["events", "batch_sums", "batch_full", "error"])
+def test_free_running_cases(lib, case, pipeline):
+    """Runs without external transfers, with the next step's random numbers
+    computed ahead (pipeline 1) or not (2): node-local events, full records,
+    weekly sums over uneven runs and a failing node, against the oracle."""
+    if case == "events":
+        spec = _no_transfers(W.config1(seed=21, Nn=900, days=80))
+        m, ref, rc = _run_both(lib, spec, 41, 3, pipeline=pipeline)
+        assert rc == 0 and ref["status"] == 0
+        _compare(m, ref, what=case)
+        c = m.counters()
+        assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+        return
+    if case == "error":
+        u0 = np.array([[500, 20, 0]] * 70 + [[50, 5, 0]])
+        spec = W.sir_spec(u0, np.arange(0, 12), 0.3, 0.1,
+                          events=W.make_events([(W.ENTER, 6, 70, 0, 3, 0.0, 0, -1),
+                                                (W.EXIT, 8, 70, 0, 400, 0.0, 0, -1)]))
+        m, ref, rc = _run_both(lib, spec, 5, 0, pipeline=pipeline)
+        info = m.error_info()
+        assert rc == ref["status"] != 0
+        assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
+        return
+    sets = W.ensemble_sets(seed=31, n_sets=6, replicates=3, days=70, nn_range=(60, 700))
+    batch = [(st.spec, 3) for st in sets]
+    record = lib.RECORD_SUMS if case == "batch_sums" else lib.RECORD_FULL
+    m = lib.Model(batch, record=record, pipeline=pipeline)
+    _say(case, m.runs, m.launch_info())
+    m.run(17, 50)
+    assert m.wait() == 0
+    sums = m.sums() if record == lib.RECORD_SUMS else None
+    for r in range(m.runs):
+        spec = sets[r // 3].spec
+        ref = oracle_run(spec, 17, 50 + r)
+        if sums is not None:
+            assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), r
+        else:
+            _compare(m, ref, run=r, what=f"batch run {r}")
