@@ -229,10 +229,12 @@ __device__ __forceinline__ int ssa_wide(const KParams& p, Node<M>& s, double t, 
     }
 }
 
-// Steps per window of the lattice walk, and the lanes its points occupy.
+// Steps per window of the lattice walk, the lanes its points occupy, and
+// the draws of one block (a whole number of windows).
 constexpr int LAT_W = 10;
 constexpr int LAT_POINTS = LAT_W * (LAT_W + 1) / 2;
-static_assert(LAT_POINTS <= WAVE, "the lattice must fit one wavefront");
+constexpr int LAT_BLOCK = 60;
+static_assert(LAT_POINTS <= WAVE && LAT_BLOCK <= WAVE && LAT_BLOCK % LAT_W == 0, "the lattice must fit one wavefront");
 
 // The same SSA for one heavy node on a whole wavefront, with the serial chain
 // cut to a few instructions per step.  With two transitions, the state k
@@ -266,13 +268,15 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
     uint32_t nd = 0, ntr = 0;  // draws and transitions, wave-uniform
     int rc = 0;
     bool done = false;
-    for (uint32_t base = 0; !done; base += WAVE) {
+    // blocks of LAT_BLOCK draws (lane j draws step base + j), walked in
+    // windows of exactly LAT_W steps
+    for (uint32_t base = 0; !done; base += LAT_BLOCK) {
         const StepRandoms mine = step_randoms(k0, k1, base + (uint32_t)lane, day_word, node, tag);
-        for (int off = 0; off < WAVE; off += LAT_W) {
-            const int wlen = WAVE - off < LAT_W ? WAVE - off : LAT_W;
+#pragma unroll 1
+        for (int off = 0; off < LAT_BLOCK; off += LAT_W) {
             // the pass: lane (lk, la) evaluates the state lk steps ahead with
             // la transitions of the first kind
-            const int src = off + (lk < wlen ? lk : 0);
+            const int src = off + (lk < LAT_W ? lk : 0);
             const double e = __shfl(mine.e, src, WAVE);
             const double r2 = __shfl(mine.r2, src, WAVE);
             int32_t uc[M::NC];
@@ -293,19 +297,6 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             // checks of the state: 1 a negative compartment, 2 a bad rate,
             // 4 lambda <= 0 (the node stops for the day)
             const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
-            // the window's first state (the day's starting state or the one
-            // the previous window ended in) is checked before its draw
-            const int c00 = __builtin_amdgcn_readfirstlane(chk);
-            if (c00) {
-                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
-                done = true;
-                break;
-            }
-            if (base + (uint32_t)off == STEP_LIMIT) {
-                rc = E_BAD_RATE;
-                done = true;
-                break;
-            }
             // The path does not depend on t: bit L of `first` says whether the
             // step from point L is of the first kind, and point (k+1, a') is
             // L + k + 1 + d.  Lane k records the point and a of step k, and
@@ -315,43 +306,61 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             int L = 0, a = 0;
 #pragma unroll
             for (int k = 0; k < LAT_W; ++k) {
-                if (k < wlen) {
-                    pidx = lane == k ? L : pidx;
-                    pa = lane == k ? a : pa;
-                    const int d = (int)((first >> L) & 1ull);
-                    a += d;
-                    L += k + 1 + d;
-                    pnext = lane == k ? L : pnext;
-                }
+                pidx = lane == k ? L : pidx;
+                pa = lane == k ? a : pa;
+                const int d = (int)((first >> L) & 1ull);
+                a += d;
+                L += k + 1 + d;
+                pnext = lane == k ? L : pnext;
             }
             const double tp = __shfl(tau, pidx, WAVE);
             const int chk_next = __shfl(chk, pnext < WAVE ? pnext : 0, WAVE);
             // the time chain, the one serial part: lane k keeps the time
             // before step k; t + tau of each step is one addition, in order
+            const double t_in = t;
             double tl = t;
 #pragma unroll
             for (int k = 0; k < LAT_W; ++k) {
-                if (k < wlen) {
-                    tl = lane == k ? t : tl;
-                    t = t + read_lane(tp, k);
-                }
+                tl = lane == k ? t : tl;
+                t = t + read_lane(tp, k);
             }
-            // first step whose draw would cross the boundary, and first step
-            // whose transition leads to a state that fails its checks (the
-            // last step's successor is checked by the next window)
-            const unsigned long long cross = __ballot(lane < wlen && tl + tp >= T);
-            const unsigned long long fail = __ballot(lane + 1 < wlen && chk_next != 0);
+            // the window's first state (the day's starting state or the one
+            // the previous window ended in) is checked before its first draw;
+            // the window's values above are then unused
+            const int c00 = __builtin_amdgcn_readfirstlane(chk);
+            if (c00) {
+                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
+                t = t_in;
+                done = true;
+                break;
+            }
+            // first step whose draw would cross the boundary, first step whose
+            // transition leads to a state that fails its checks (the last
+            // step's successor is checked by the next window), and the step
+            // whose draw would exceed the step limit
+            const unsigned long long cross = __ballot(lane < LAT_W && tl + tp >= T);
+            const unsigned long long fail = __ballot(lane + 1 < LAT_W && chk_next != 0);
             const int kc = cross ? __builtin_ctzll(cross) : WAVE;
             const int kf = fail ? __builtin_ctzll(fail) : WAVE;
+            const uint32_t g = base + (uint32_t)off;
+            const int kl = g <= STEP_LIMIT && STEP_LIMIT - g < (uint32_t)LAT_W ? (int)(STEP_LIMIT - g) : WAVE;
             int kend, aend;
-            if (kc <= kf && kc < wlen) {
+            if (kl < LAT_W && kl <= kc && kl <= kf) {
+                // the draw with index STEP_LIMIT: the node's rates are unusable
+                kend = kl;
+                aend = __builtin_amdgcn_readlane(pa, kl);
+                nd += (uint32_t)kl;
+                ntr += (uint32_t)kl;
+                rc = E_BAD_RATE;
+                done = true;
+            } else if (kc <= kf && kc < LAT_W) {
                 // stops at the boundary before the transition of step kc
                 kend = kc;
                 aend = __builtin_amdgcn_readlane(pa, kc);
                 nd += (uint32_t)kc + 1u;
                 ntr += (uint32_t)kc;
                 done = true;
-            } else if (kf < wlen) {
+            } else if (kf < LAT_W) {
                 // the transition of step kf leads to a failing state
                 kend = kf + 1;
                 aend = __builtin_amdgcn_readlane(pa, kf + 1);
@@ -361,10 +370,10 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
                 ntr += (uint32_t)kf + 1u;
                 done = true;
             } else {
-                kend = wlen;
+                kend = LAT_W;
                 aend = a;
-                nd += (uint32_t)wlen;
-                ntr += (uint32_t)wlen;
+                nd += (uint32_t)LAT_W;
+                ntr += (uint32_t)LAT_W;
             }
 #pragma unroll
             for (int c = 0; c < M::NC; ++c) s.u[c] += aend * S0[c] + (kend - aend) * S1[c];

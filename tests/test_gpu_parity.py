@@ -265,13 +265,14 @@ def test_wait_limit_abandons_run_cleanly(lib):
 
 @pytest.mark.parametrize("lattice", [1, 2])
 @pytest.mark.parametrize("case", ["extinction", "immigration", "sise", "sir_heavy", "neg_state", "bad_rate",
-                                  "step_limit"])
+                                  "step_limit", "step_limit_full_g"])
 def test_wide_node_paths(lib, case, lattice):
     """Every node on its own wavefront (lanes=64, wide=Nn), with the lattice
     walk (1) and the plain dependent chain (2): stops at lambda = 0 inside a
     window, thousands of steps per day, the SISe rates, an epidemic's
     turnover, a negative compartment after a transition, a bad rate, and the
-    2^24-step guard, all against the oracle (state, counters, error key)."""
+    2^24-step guard (in both paths), all against the oracle (state, counters,
+    error key)."""
     rng = np.random.default_rng(17)
     tspan = np.arange(0, 6)
     if case == "extinction":
@@ -289,6 +290,10 @@ def test_wide_node_paths(lib, case, lattice):
         spec.S = np.array([[-1, 0], [1, -1], [-1, 1]])   # an infection also removes a recovered
     elif case == "bad_rate":
         spec = W.sir_spec(np.array([[500, 20, 0], [300, 4, 3]]), tspan, -0.4, 0.1)
+    elif case == "step_limit_full_g":
+        # SIS marks both rates after either transition, so the lattice walk
+        # runs into the 2^24-draw guard (about 1e8 transitions per day)
+        spec = W.sis_spec(np.array([[100000, 100000]]), np.arange(0, 2), 0.01, 0.5)
     else:
         spec = W.birth_death_spec(np.array([0, 0]), np.arange(0, 2), 3.0e7, 0.0, immigration=True)
     Nn = np.asarray(spec.u0).shape[0]
