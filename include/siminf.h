@@ -145,6 +145,14 @@ typedef struct {
                           transfer) may take before the run is abandoned with
                           SIMINF_E_DEVICE; 0 = 60000.  Legitimate waits can last
                           as long as the slowest node's share of the run. */
+    int32_t graph;     /* 1: the first siminf_run captures the run's launches in a
+                          HIP graph and every run replays it (the seed and stream
+                          base are read from device memory); only for models
+                          without external transfers, else siminf_run returns
+                          SIMINF_E_UNSUPPORTED.  Reconfiguring (siminf_autotune)
+                          drops the graph.  siminf_timing's kernel time then also
+                          covers the short init kernel.  0 (default): plain
+                          launches. */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;

@@ -40,6 +40,14 @@ struct Ctrl {
     unsigned int pad;
 };
 
+// The per-run values a launch reads from device memory rather than from its
+// arguments, so that a captured launch sequence serves every run.
+struct RunParams {
+    unsigned long long seed;
+    unsigned int stream_base;
+    unsigned int pad;
+};
+
 // One scheduled event, packed for a single 16-byte load:
 //   x = time, y = type | select mask << 2 | target(c) << (6 + 2c), z = n,
 //   w = input index within its spec (the sampling RNG's identity)
@@ -120,6 +128,7 @@ struct KParams {
     int32_t nbig;                // the first nbig nodes each get a whole wavefront
     int32_t lattice;             // wide nodes walk a lattice of reachable states
     uint64_t wait_ticks;         // wall-clock ticks one wait may last before abort
+    const RunParams* rp;         // seed and stream base of the current run (device)
 };
 
 // Launchers implemented in ssa_kernels.hip.

@@ -85,9 +85,21 @@ struct siminf_model {
     uint64_t counters[4] = {0, 0, 0, 0};
     siminf_options opt{};
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // run start, SSA kernels start, run end
+    RunParams* d_rp = nullptr;  // the run's seed and stream base, read by the kernels
+    RunParams* h_rp = nullptr;  // pinned host staging of d_rp
+    hipGraph_t graph = nullptr;  // options.graph: the captured init and SSA launches
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
+
+// Drops the captured launch sequence (the launch configuration changed).
+void drop_graph(siminf_model* m) {
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    m->gexec = nullptr;
+    m->graph = nullptr;
+}
 
 int hip_fail(siminf_model* m) {
     if (m) m->status = SIMINF_E_DEVICE;
@@ -201,6 +213,7 @@ int default_wide(const siminf_model* m, const Group& g, int div = 16) {
 // external transfers: 0 auto (dataflow if every node wavefront and the worker
 // fit on the device at once, else grid barrier), 1 barrier, 2 dataflow.
 int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode) {
+    drop_graph(m);
     KParams& p = g.p;
     const int n = g.n;
     const int cus = device_cus(m);
@@ -273,7 +286,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         return SIMINF_E_ARG;
     }
     if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2 || m->opt.wait_ms < 0 ||
-        m->opt.lattice < 0 || m->opt.lattice > 2) {
+        m->opt.lattice < 0 || m->opt.lattice > 2 || m->opt.graph < 0 || m->opt.graph > 1) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -388,6 +401,8 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
     int32_t *d_run_spec, *d_rec_off;
     if (to_device(m->owned, gdata, &d_gdata) || to_device(m->owned, run_spec, &d_run_spec) ||
         to_device(m->owned, m->rec_off, &d_rec_off))
+        return hip_fail(m);
+    if (alloc_device(m->owned, 1, &m->d_rp) || hipHostMalloc((void**)&m->h_rp, sizeof(RunParams)) != hipSuccess)
         return hip_fail(m);
     if (alloc_device(m->owned, 1, &m->d_ctrl) || hipMemset(m->d_ctrl, 0, sizeof(Ctrl)) != hipSuccess)
         return hip_fail(m);
@@ -728,6 +743,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 return hip_fail(m);
         }
         p.ctrl = m->d_ctrl;
+        p.rp = m->d_rp;
         p.group = (int)gi;
         if (g.n_e2 > 0) {
             // live state for the transfer kernels (both variants)
@@ -807,30 +823,84 @@ int siminf_create_batch(const siminf_spec* specs, int32_t nspecs, const int32_t*
     return create_impl(specs, nspecs, replicates, opt, out);
 }
 
-int siminf_run(siminf_model* m, uint64_t seed, uint32_t stream_base, void* hip_stream) {
-    if (!m) return SIMINF_E_ARG;
-    if ((uint64_t)stream_base + (uint64_t)m->R > (1ull << 24)) return SIMINF_E_ARG;
-    if (m->pending) finish(m);
-    hipStream_t st = (hipStream_t)hip_stream;
-    if (hipEventRecord(m->ev[0], st) != hipSuccess) return hip_fail(m);
+namespace {
+
+// The launches of one run after its parameters are in place: the init
+// kernel(s), then (mark recorded on the stream between them if given) one
+// SSA kernel per group.
+int enqueue_launches(siminf_model* m, hipStream_t st, hipEvent_t mark = nullptr) {
     for (size_t gi = 0; gi < m->groups.size(); ++gi) {
         Group& g = m->groups[gi];
-        g.p.seed = seed;
-        g.p.stream_base = stream_base;
         if (launch_init(g.p, g.shape.nc, g.shape.nv, m->first_rec, gi == 0,
                         gi == 0 ? m->d_sums_init : nullptr, gi == 0 ? m->sums_len : 0, st) != hipSuccess)
-            return hip_fail(m);
+            return SIMINF_E_DEVICE;
     }
     if (m->groups.empty()) {
         KParams p{};
         p.ctrl = m->d_ctrl;
         p.sums = m->d_sums;
-        if (launch_init(p, 0, 0, 0, true, m->d_sums_init, m->sums_len, st) != hipSuccess) return hip_fail(m);
+        p.rp = m->d_rp;
+        if (launch_init(p, 0, 0, 0, true, m->d_sums_init, m->sums_len, st) != hipSuccess) return SIMINF_E_DEVICE;
     }
-    if (hipEventRecord(m->ev[1], st) != hipSuccess) return hip_fail(m);
+    if (mark && hipEventRecord(mark, st) != hipSuccess) return SIMINF_E_DEVICE;
     for (Group& g : m->groups) {
         if (g.n == 0) continue;
-        if (launch_group(g.model, g.p, g.block, g.blocks, g.shmem, st) != hipSuccess) return hip_fail(m);
+        if (launch_group(g.model, g.p, g.block, g.blocks, g.shmem, st) != hipSuccess) return SIMINF_E_DEVICE;
+    }
+    return SIMINF_OK;
+}
+
+// Captures enqueue_launches on a private stream into an executable graph.
+int capture_graph(siminf_model* m) {
+    for (const Group& g : m->groups)
+        if (g.n > 0 && g.p.mode != MODE_FREE) return SIMINF_E_UNSUPPORTED;  // cooperative launches
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return SIMINF_E_DEVICE;
+    int rc = SIMINF_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = SIMINF_E_DEVICE;
+    } else {
+        rc = enqueue_launches(m, cs);
+        hipGraph_t graph = nullptr;
+        if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) {
+            rc = SIMINF_E_DEVICE;
+        } else if (rc == SIMINF_OK && hipGraphInstantiate(&m->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            m->gexec = nullptr;
+            rc = SIMINF_E_DEVICE;
+        }
+        m->graph = graph;
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != SIMINF_OK) drop_graph(m);
+    return rc;
+}
+
+}  // namespace
+
+int siminf_run(siminf_model* m, uint64_t seed, uint32_t stream_base, void* hip_stream) {
+    if (!m) return SIMINF_E_ARG;
+    if ((uint64_t)stream_base + (uint64_t)m->R > (1ull << 24)) return SIMINF_E_ARG;
+    if (m->pending) finish(m);  // the staging buffer and the device state are free again
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (m->opt.graph && !m->gexec) {
+        const int rc = capture_graph(m);
+        if (rc != SIMINF_OK) {
+            m->status = rc;
+            return rc;
+        }
+    }
+    m->h_rp->seed = seed;
+    m->h_rp->stream_base = stream_base;
+    m->h_rp->pad = 0;
+    if (hipEventRecord(m->ev[0], st) != hipSuccess ||
+        hipMemcpyAsync(m->d_rp, m->h_rp, sizeof(RunParams), hipMemcpyHostToDevice, st) != hipSuccess)
+        return hip_fail(m);
+    if (m->gexec) {
+        // the graph holds the init kernels too: timed with the SSA kernels
+        if (hipEventRecord(m->ev[1], st) != hipSuccess || hipGraphLaunch(m->gexec, st) != hipSuccess)
+            return hip_fail(m);
+    } else if (enqueue_launches(m, st, m->ev[1]) != SIMINF_OK) {
+        return hip_fail(m);
     }
     if (hipEventRecord(m->ev[2], st) != hipSuccess) return hip_fail(m);
     m->last_stream = st;
@@ -1004,6 +1074,8 @@ void siminf_destroy(siminf_model* m) {
     if (m->pending) finish(m);
     for (hipEvent_t e : m->ev)
         if (e) (void)hipEventDestroy(e);
+    drop_graph(m);
+    if (m->h_rp) (void)hipHostFree(m->h_rp);
     for (void* p : m->owned) (void)hipFree(p);
     delete m;
 }

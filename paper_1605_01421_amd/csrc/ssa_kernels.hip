@@ -564,7 +564,10 @@ __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, 
 // free-running kernel (no external transfers)
 // ---------------------------------------------------------------------------
 template <class M, bool PIPE>
-__global__ void __launch_bounds__(256) free_kernel(KParams p) {
+__global__ void __launch_bounds__(256) free_kernel(KParams pa) {
+    KParams p = pa;
+    p.seed = pa.rp->seed;
+    p.stream_base = pa.rp->stream_base;
     const int lane = threadIdx.x & (WAVE - 1);
     Tally t;
     for (;;) {
@@ -645,7 +648,10 @@ __device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long
 }
 
 template <class M, bool PIPE>
-__global__ void __launch_bounds__(256) flow_kernel(KParams p) {
+__global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
+    KParams p = pa;
+    p.seed = pa.rp->seed;
+    p.stream_base = pa.rp->stream_base;
     Tally t;
     const int lane = threadIdx.x & (WAVE - 1);
     const int gw = blockIdx.x * (blockDim.x / WAVE) + (int)(threadIdx.x / WAVE);
@@ -788,7 +794,10 @@ __device__ __forceinline__ void load_live(const KParams& p, Node<M>& s, int k) {
 }
 
 template <class M, bool PIPE>
-__global__ void __launch_bounds__(256) sync_kernel(KParams p) {
+__global__ void __launch_bounds__(256) sync_kernel(KParams pa) {
+    KParams p = pa;
+    p.seed = pa.rp->seed;
+    p.stream_base = pa.rp->stream_base;
     const int lane = threadIdx.x & (WAVE - 1);
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nthreads = gridDim.x * blockDim.x;

@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
     _fields_ = [("record", ctypes.c_int32), ("block", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32), ("mode", ctypes.c_int32), ("wide", ctypes.c_int32),
-                ("lattice", ctypes.c_int32), ("wait_ms", ctypes.c_int32)]
+                ("lattice", ctypes.c_int32), ("wait_ms", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 # exported entry points: name -> (restype, argtypes)
@@ -169,11 +169,11 @@ class Model:
 
     def __init__(self, spec, record: int = RECORD_FULL, block: int = 0, order: int = 0,
                  lanes: int = 0, max_blocks: int = 0, pipeline: int = 0, mode: int = 0, wide: int = 0,
-                 lattice: int = 0, wait_ms: int = 0):
+                 lattice: int = 0, wait_ms: int = 0, graph: int = 0):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p()
-        opt = Options(record, block, order, lanes, max_blocks, pipeline, mode, wide, lattice, wait_ms)
+        opt = Options(record, block, order, lanes, max_blocks, pipeline, mode, wide, lattice, wait_ms, graph)
         keep: list = []
         if isinstance(spec, (list, tuple)):
             specs = [s for s, _ in spec]
