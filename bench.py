@@ -3,16 +3,18 @@
 
 One step = one complete run of the SIR model with scheduled events on 10,000
 nodes over 365 days (SSA to every day boundary, exit/enter events per node,
-external transfers in conflict levels, record of U every day), inputs
-resident in device memory.  Prints one JSON line:
+external transfers between nodes, record of U every day), inputs resident in
+device memory.  Prints one JSON line:
 
   value            node-days per second over the timed steps (wall clock,
                    bracketed by device synchronisation)
   transitions_per_s executed transitions per second
   roofline         the SSA kernel against the VALU peak (see OPS_PER_STEP)
+  hbm_roofline     transitions/s against the bytes-per-transition HBM bound
   cpu_baseline     the CPU oracle (OpenMP) on the same workload
 
   python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+  python bench.py --workload ensemble|sise-events|sir-plain|mlp
 """
 from __future__ import annotations
 
@@ -21,6 +23,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -74,6 +78,30 @@ def measured_traffic(kernel: str, workload: str):
 
 
 MODEL_NAMES = {0: "SIR", 1: "SIS", 2: "SISe", 3: "birth-death", 4: "immigration-death"}
+HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E (published)
+
+
+def algorithmic_bytes(spec, record_sums: bool) -> float:
+    """HBM bytes one run (or batch) must move at least: node data read once
+    (state, continuous state, local data and three 4-byte identities), node-
+    local event records (16 B) read once, each external transfer's two
+    per-node items and records (2 x 32 B), and the records written: per node
+    and record 4 B per compartment and 8 B per continuous variable, or, for a
+    batch recorded as sums, 8 B per run, record and compartment."""
+    runs = spec if isinstance(spec, list) else [(spec, 1)]
+    total = 0.0
+    for sp, reps in runs:
+        nn, nc = sp.Nn, int(np.asarray(sp.S).shape[0])
+        nv = int(np.asarray(sp.v0).reshape(nn, -1).shape[1]) if nn else 0
+        nld = int(np.asarray(sp.ldata).reshape(nn, -1).shape[1]) if nn else 0
+        ev = np.asarray(sp.events["event"])
+        n_e2 = int((ev == 3).sum())
+        n_e1 = int(ev.size) - n_e2
+        ntspan = int(np.asarray(sp.tspan).size)
+        per_run = nn * (4 * nc + 8 * (nv + nld) + 12) + 16 * n_e1 + 64 * n_e2
+        per_run += 8 * ntspan * nc if record_sums else ntspan * nn * (4 * nc + 8 * nv)
+        total += reps * per_run
+    return float(total)
 
 
 def build_workload(name):
@@ -303,6 +331,15 @@ def main():
                      "kernel": ["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
                      "ssa_steps_per_launch": draws_per_launch, "ops_per_step": OPS_PER_STEP},
     }
+    alg = algorithmic_bytes(spec, batch)
+    per_tr = alg / max(transitions / args.steps, 1.0)
+    traffic = out["roofline"]["traffic"]
+    out["hbm_roofline"] = {
+        "algorithmic_bytes_per_launch": alg, "bytes_per_transition": per_tr,
+        "transitions_per_s_at_peak": HBM_PEAK / per_tr,
+        "frac": (transitions / wall) / (HBM_PEAK / per_tr),
+        "measured_gb_per_s": traffic / mean_kernel_s / 1e9 if traffic else None,
+        "peak_gb_per_s": HBM_PEAK / 1e9}
     if not args.no_cpu:
         if batch:
             out["cpu_baseline"] = cpu_baseline_batch(spec, seed0 + args.steps - 1, args.cpu_seconds, model.sums())

@@ -354,3 +354,25 @@ def test_free_running_cases(lib, case, pipeline):
             assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), r
         else:
             _compare(m, ref, run=r, what=f"batch run {r}")
+
+
+def test_split_run_equals_full_run(lib):
+    """Draws are keyed by the absolute day: running [0, 40] and then
+    [40, 90] from the saved state equals one run over [0, 90] on the GPU
+    (SIR and SISe, with phi carried over)."""
+    def go(spec, seed, stream):
+        m = lib.Model(spec)
+        m.run(seed, stream)
+        assert m.wait() == 0
+        return m.trajectory()
+    u0 = np.tile([300, 5, 0], (50, 1))
+    U, _ = go(W.sir_spec(u0, np.arange(0, 91), 0.3, 0.1), 11, 2)
+    U1, _ = go(W.sir_spec(u0, np.arange(0, 41), 0.3, 0.1), 11, 2)
+    U2, _ = go(W.sir_spec(U1[-1], np.arange(40, 91), 0.3, 0.1), 11, 2)
+    assert np.array_equal(U[:41], U1) and np.array_equal(U[40:], U2)
+    su = np.tile([60, 4], (30, 1))
+    bq = (0.1, 0.12, 0.1, 0.11)
+    F, FV = go(W.sise_spec(su, np.arange(0, 91), 0.02, 0.1, 1.0, bq), 3, 0)
+    S1, S1V = go(W.sise_spec(su, np.arange(0, 41), 0.02, 0.1, 1.0, bq), 3, 0)
+    S2, S2V = go(W.sise_spec(S1[-1], np.arange(40, 91), 0.02, 0.1, 1.0, bq, phi0=S1V[-1, :, 0]), 3, 0)
+    assert np.array_equal(F[40:], S2) and np.array_equal(FV[40:], S2V)
