@@ -45,6 +45,11 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 SSA_SOURCES = ("device_math.h", "internal.h", "models.h", "runtime.cpp", "ssa_kernels.hip")
 
 
+def _progress(*a):
+    """A progress line on stderr (the result line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     """sha256 over the sources that decide the SSA kernels' code and data
     layout (the network's file is left out: it does not touch them)."""
@@ -243,6 +248,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per node: 0 auto, 1, 64")
     ap.add_argument("--wide", type=int, default=0, help="with --lanes 64: wavefront-wide nodes")
     ap.add_argument("--pipeline", type=int, default=0, help="0 auto, 1 on, 2 off")
+    ap.add_argument("--pack", type=int, default=0, help="nodes per one-lane-per-node wavefront: 0 auto, 4, 8, 16, 32, 64")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="replay the run from a captured HIP graph: 1 on, 0 off, -1 on for batches without transfers")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (launch shape from heuristics)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -264,17 +272,30 @@ def main():
         return
     torch.cuda.set_device(0)
     spec, desc = build_workload(args.workload)
+    _progress("workload built:", desc["workload"])
     batch = isinstance(spec, list)
+    graph = args.graph if args.graph >= 0 else int(batch)
     model = siminf.Model(spec, record=siminf.RECORD_SUMS if batch else siminf.RECORD_FULL, block=args.block,
-                         order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline)
+                         order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline,
+                         pack=args.pack, graph=graph)
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
-        tuned_ms = model.autotune(seed=seed0 - 1000, repeats=2)
+        # one plain run first: long runs are tuned on one repeat per shape
+        model.run(seed0 - 2000)
+        assert model.wait() == 0, model.error_info()
+        probe_ms = model.timing()["kernel_ms"]
+        repeats = 1 if probe_ms > 500 else 2
+        if probe_ms > 500:
+            os.environ["SIMINF_AUTOTUNE_LOG"] = "1"  # a line per shape: long tunes keep printing
+        _progress(f"autotuning ({probe_ms:.1f} ms per run, {repeats} repeat(s) per shape)")
+        tuned_ms = model.autotune(seed=seed0 - 1000, repeats=repeats)
+        _progress("autotuned:", model.launch_info(), f"{tuned_ms:.3f} ms")
     for w in range(args.warmup):
         model.run(seed0 - 1 - w)
         assert model.wait() == 0, model.error_info()
     torch.cuda.synchronize()
+    _progress(f"warm-up done; timing {args.steps} steps")
 
     kernel_ms, node_days, transitions, draws, events = [], 0, 0, 0, 0
     first_counters = None
@@ -319,7 +340,7 @@ def main():
         "data": "synthetic",
         "config": dict(desc, seed=seed0, block=info["block"], blocks=info["blocks"],
                        kernel=["free-running", "grid-barrier", "dataflow"][info["mode"]],
-                       wide_nodes=info["wide"], pipeline=info["pipeline"]),
+                       wide_nodes=info["wide"], pipeline=info["pipeline"], pack=info["pack"], graph=graph),
         "transitions_per_s": transitions / wall,
         "events_per_step": events / args.steps,
         "kernel_ms_mean": mean_kernel_s * 1e3,
@@ -341,6 +362,7 @@ def main():
         "measured_gb_per_s": traffic / mean_kernel_s / 1e9 if traffic else None,
         "peak_gb_per_s": HBM_PEAK / 1e9}
     if not args.no_cpu:
+        _progress(f"GPU timing done ({mean_kernel_s * 1e3:.3f} ms per run); CPU oracle baseline")
         if batch:
             out["cpu_baseline"] = cpu_baseline_batch(spec, seed0 + args.steps - 1, args.cpu_seconds, model.sums())
         else:

@@ -125,7 +125,8 @@ typedef struct {
 /* Launch and recording options; a zeroed struct (or NULL) gives defaults. */
 typedef struct {
     int32_t record;    /* SIMINF_RECORD_FULL (default) or SIMINF_RECORD_SUMS */
-    int32_t block;     /* threads per workgroup, multiple of 64 up to 1024; 0 = tuned */
+    int32_t block;     /* threads per workgroup: 64, 128, 192 or 256; 0 = chosen
+                          from the model (64 with external transfers, else 256) */
     int32_t order;     /* lane order: 0 = binned by expected work (default), 1 = input order */
     int32_t lanes;     /* lanes per node: 0 auto, 1 one lane for every node, 64 the
                           heaviest nodes get a whole wavefront (its 64 lanes draw
@@ -153,6 +154,14 @@ typedef struct {
                           drops the graph.  siminf_timing's kernel time then also
                           covers the short init kernel.  0 (default): plain
                           launches. */
+    int32_t pack;      /* nodes in a wavefront that gives each node one lane: 64,
+                          32, 16, 8 or 4 (the remaining lanes idle); 0 = 64.  Fewer
+                          nodes per wavefront shorten a latency-bound run (each
+                          wavefront's day ends with its slowest node, and an
+                          external transfer holds back only the destination's
+                          wavefront) when the device has SIMDs to spare.  The
+                          grid-barrier kernel always packs 64; the results do
+                          not depend on it. */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;
@@ -217,16 +226,22 @@ int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32
 /* Launch configuration chosen for the handle (its first model group):
  * out[0] threads per block, out[1] blocks, out[2] kernel (0 free-running,
  * 1 grid-barrier, 2 dataflow), out[3] pipelining on/off, out[4] order,
- * out[5] nodes carried by a whole wavefront. */
-int siminf_launch_info(const siminf_model *m, int32_t out[6]);
+ * out[5] nodes carried by a whole wavefront, out[6] nodes per wavefront of
+ * the others (the pack option). */
+int siminf_launch_info(const siminf_model *m, int32_t out[7]);
 
 /* Autotuner: runs the model `repeats` times for each candidate launch shape
  * (threads per block 64/128/256; no wavefront-wide nodes, or those whose
  * expected work exceeds 1/4, 1/16 or 1/64 of the heaviest node's;
  * pipelining on/off), on hip_stream with seeds seed, seed+1, ..., and keeps
  * the shape with the smallest lower-median SSA-kernel time (the faster of
- * two repeats; written to *best_ms if not NULL).  Every shape gives
- * bit-identical results; the handle's recorded results are overwritten. */
+ * two repeats; written to *best_ms if not NULL).  With pack = 0 and fewer
+ * nodes than the device has SIMDs times 64, it then tries 32, 16, 8 and 4
+ * nodes per wavefront on the best shape and, if one of those wins, the four
+ * wide-node choices again with it.  Every shape gives bit-identical results;
+ * the handle's recorded results are overwritten.  With the environment
+ * variable SIMINF_AUTOTUNE_LOG set (and not "0"), each candidate's time is
+ * printed to stderr as it is measured. */
 int siminf_autotune(siminf_model *m, uint64_t seed, int32_t repeats, void *hip_stream, double *best_ms);
 
 /* Device time of the last run, from HIP events the library records on the

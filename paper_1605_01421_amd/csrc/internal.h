@@ -122,7 +122,9 @@ struct KParams {
     unsigned long long* sums;    // [runs][ntspan][sums_nc]
     Ctrl* ctrl;
     int32_t group;
-    int32_t nchunks;             // 64-node chunks (free-running work queue)
+    int32_t nchunks;             // chunks of the free-running work queue
+    int32_t pack;                // nodes per wavefront that carries one lane per node
+                                 // (64, 32, 16, 8 or 4; the other lanes idle)
     int32_t nblocks;
     int32_t pipeline;            // 1: overlap the next step's random numbers with this step
     int32_t nbig;                // the first nbig nodes each get a whole wavefront

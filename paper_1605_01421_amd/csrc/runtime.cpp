@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -212,13 +214,14 @@ int default_wide(const siminf_model* m, const Group& g, int div = 16) {
 // Kernel and launch shape of one group.  want_mode applies to groups with
 // external transfers: 0 auto (dataflow if every node wavefront and the worker
 // fit on the device at once, else grid barrier), 1 barrier, 2 dataflow.
-int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode) {
+int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode, int pack) {
     drop_graph(m);
     KParams& p = g.p;
     const int n = g.n;
     const int cus = device_cus(m);
     if (cus <= 0) return SIMINF_E_DEVICE;
     nbig = std::max(0, std::min(nbig, n));
+    if (pack != 4 && pack != 8 && pack != 16 && pack != 32) pack = WAVE;
     // pipelining pays where lanes are scarce (latency-bound runs); with many
     // waves per SIMD the extra, unused last draw of each node-day only costs
     const int simd_lanes = cus * 4 * WAVE;
@@ -231,7 +234,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         if (want_mode == 0 || want_mode == 2) {
             const int per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, block, 0);
             int nb = nbig;
-            auto need = [&](int k) { return (k + (n - k + WAVE - 1) / WAVE + wpb - 1) / wpb; };
+            auto need = [&](int k) { return (k + (n - k + pack - 1) / pack + wpb - 1) / wpb; };
             while (nb > 0 && per_cu > 0 && need(nb) > per_cu * cus) nb /= 2;
             if (per_cu > 0 && need(nb) <= per_cu * cus) {
                 mode = MODE_FLOW;
@@ -245,6 +248,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
             mode = MODE_BARRIER;
             shmem = 0;
             nbig = 0;
+            pack = WAVE;  // the barrier kernel strides over nodes 64 to a wavefront
             const int per_cu = max_blocks_per_cu(g.model, MODE_BARRIER, p.pipeline, block, 0);
             if (per_cu <= 0) return SIMINF_E_DEVICE;
             blocks = std::max(1, std::min(per_cu * cus, (n + block - 1) / block));
@@ -253,14 +257,15 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     } else {
         const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, p.pipeline, block, 0);
         if (per_cu <= 0) return SIMINF_E_DEVICE;
-        const int chunks = nbig + (n - nbig + WAVE - 1) / WAVE;
+        const int chunks = nbig + (n - nbig + pack - 1) / pack;
         blocks = std::max(1, std::min(per_cu * cus, (chunks + wpb - 1) / wpb));
         if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
     }
     g.mode = mode;
     p.mode = mode;
     p.nbig = nbig;
-    p.nchunks = nbig + (n - nbig + WAVE - 1) / WAVE;
+    p.pack = pack;
+    p.nchunks = nbig + (n - nbig + pack - 1) / pack;
     g.block = block;
     g.blocks = blocks;
     g.shmem = shmem;
@@ -287,6 +292,11 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
     }
     if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2 || m->opt.wait_ms < 0 ||
         m->opt.lattice < 0 || m->opt.lattice > 2 || m->opt.graph < 0 || m->opt.graph > 1) {
+        set_create_error(m, SIMINF_E_ARG, -1, -1);
+        return SIMINF_E_ARG;
+    }
+    if (m->opt.pack != 0 && m->opt.pack != 4 && m->opt.pack != 8 && m->opt.pack != 16 && m->opt.pack != 32 &&
+        m->opt.pack != 64) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -752,7 +762,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 alloc_device(m->owned, (size_t)p.n_e2 * MAX_NC, &p.mail_big))
                 return hip_fail(m);
         }
-        const int rc = configure(m, g, m->opt.block, default_wide(m, g), m->opt.pipeline, m->opt.mode);
+        const int rc = configure(m, g, m->opt.block, default_wide(m, g), m->opt.pipeline, m->opt.mode, m->opt.pack);
         if (rc) {
             set_create_error(m, rc, -1, -1);
             return rc;
@@ -994,10 +1004,10 @@ int siminf_error_info(const siminf_model* m, int32_t* code, int64_t* step, int32
     return SIMINF_OK;
 }
 
-int siminf_launch_info(const siminf_model* m, int32_t out[6]) {
+int siminf_launch_info(const siminf_model* m, int32_t out[7]) {
     if (!m || !out) return SIMINF_E_ARG;
     if (m->groups.empty()) {
-        for (int i = 0; i < 6; ++i) out[i] = 0;
+        for (int i = 0; i < 7; ++i) out[i] = 0;
         return SIMINF_OK;
     }
     const Group& g = m->groups[0];
@@ -1007,6 +1017,7 @@ int siminf_launch_info(const siminf_model* m, int32_t out[6]) {
     out[3] = g.p.pipeline;
     out[4] = m->opt.order;
     out[5] = g.p.nbig;
+    out[6] = g.p.pack;
     return SIMINF_OK;
 }
 
@@ -1015,43 +1026,69 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     if (m->groups.empty()) return SIMINF_OK;
     finish(m);
     struct Cand {
-        int block, wide_div, pipeline;
+        int block, wide_div, pipeline, pack;
     };
-    std::vector<Cand> cands;
-    for (int block : {64, 128, 256})
-        for (int div : {0, 4, 16, 64})  // wide nodes: none, or work above 1/div of the heaviest
-            for (int pipe : {1, 2}) cands.push_back({block, div, pipe});
-    double best = 1e300;
-    Cand pick = cands[0];
-    bool any = false;
-    for (const Cand& c : cands) {
-        bool ok = true;
+    // lower-median SSA-kernel time of one candidate over `repeats` runs, or a
+    // negative value if it cannot be launched
+    auto measure = [&](const Cand& c) -> double {
         for (Group& g : m->groups) {
             const int nb = default_wide(m, g, c.wide_div);
-            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode) != SIMINF_OK) ok = false;
+            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode, c.pack) != SIMINF_OK) return -1.0;
         }
-        if (!ok) continue;
         std::vector<double> t;
-        for (int r = 0; r < repeats && ok; ++r) {
+        for (int r = 0; r < repeats; ++r) {
             double ms[2];
             if (siminf_run(m, seed + (uint64_t)r, 0, hip_stream) != SIMINF_OK || finish(m) != SIMINF_OK ||
                 siminf_timing(m, ms) != SIMINF_OK)
-                ok = false;
-            else
-                t.push_back(ms[0]);
+                return -1.0;
+            t.push_back(ms[0]);
         }
-        if (!ok) continue;
         std::sort(t.begin(), t.end());
-        const double med = t[(t.size() - 1) / 2];  // lower median: the faster of two repeats
-        if (med < best) {
-            best = med;
+        return t[(t.size() - 1) / 2];  // lower median: the faster of two repeats
+    };
+    const int pack0 = m->opt.pack ? m->opt.pack : WAVE;
+    std::vector<Cand> cands;
+    for (int block : {64, 128, 256})
+        for (int div : {0, 4, 16, 64})  // wide nodes: none, or work above 1/div of the heaviest
+            for (int pipe : {1, 2}) cands.push_back({block, div, pipe, pack0});
+    double best = 1e300;
+    Cand pick = cands[0];
+    bool any = false;
+    const char* log_env = std::getenv("SIMINF_AUTOTUNE_LOG");
+    const bool log = log_env && log_env[0] && log_env[0] != '0';
+    auto consider = [&](const Cand& c) {
+        const double t = measure(c);
+        if (log) {
+            std::fprintf(stderr, "siminf_autotune: block %d wide_div %d pipeline %d pack %d: %.3f ms\n", c.block,
+                         c.wide_div, c.pipeline, c.pack, t);
+            std::fflush(stderr);
+        }
+        if (t >= 0.0 && t < best) {
+            best = t;
             pick = c;
             any = true;
         }
-    }
+    };
+    for (const Cand& c : cands) consider(c);
     if (!any) return SIMINF_E_DEVICE;
+    // Packing fewer nodes into a wavefront only pays when the device has more
+    // SIMDs than a full packing fills: then each wavefront's day ends with the
+    // slowest of fewer nodes, and a transfer holds back fewer of them.  Tried
+    // on the best shape of the first sweep; the share of wavefront-wide nodes
+    // is then tuned again, since cheaper narrow nodes move its optimum.
+    long long lanes_needed = 0;
+    for (const Group& g : m->groups) lanes_needed += g.n;
+    if (m->opt.pack == 0 && (lanes_needed + WAVE - 1) / WAVE < (long long)device_cus(m) * 4) {
+        const Cand first = pick;
+        for (int pack : {32, 16, 8, 4}) consider({first.block, first.wide_div, first.pipeline, pack});
+        if (pick.pack != first.pack) {
+            const Cand second = pick;
+            for (int div : {0, 4, 16, 64})
+                if (div != second.wide_div) consider({second.block, div, second.pipeline, second.pack});
+        }
+    }
     for (Group& g : m->groups) {
-        configure(m, g, pick.block, default_wide(m, g, pick.wide_div), pick.pipeline, m->opt.mode);
+        configure(m, g, pick.block, default_wide(m, g, pick.wide_div), pick.pipeline, m->opt.mode, pick.pack);
     }
     if (best_ms) *best_ms = best;
     return SIMINF_OK;

@@ -299,9 +299,51 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
             // The path does not depend on t: bit L of `first` says whether the
             // step from point L is of the first kind, and point (k+1, a') is
-            // L + k + 1 + d.  Lane k records the point and a of step k, and
-            // the point the step leads to.
+            // L + k + 1 + d.
             const unsigned long long first = __ballot(n == 0);
+            // the window's first state (the day's starting state or the one
+            // the previous window ended in) is checked before its first draw;
+            // the window's values above are then unused
+            const int c00 = __builtin_amdgcn_readfirstlane(chk);
+            if (c00) {
+                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
+                done = true;
+                break;
+            }
+            // Fast path, taken by every window but the day's last: the path in
+            // scalar registers, tau read from the lane of each point in turn.
+            // When every state on the path passes its checks, each tau is
+            // finite and >= 0, so the times only grow and a window that ends
+            // before T crosses nowhere.
+            const double t_in = t;
+            {
+                int pl[LAT_W];
+                int L = 0, a = 0;
+                unsigned long long onpath = 0;  // path points 1 .. LAT_W-1
+#pragma unroll
+                for (int k = 0; k < LAT_W; ++k) {
+                    pl[k] = L;
+                    if (k > 0) onpath |= 1ull << L;
+                    const int d = (int)((first >> L) & 1ull);
+                    a += d;
+                    L += k + 1 + d;
+                }
+                const unsigned long long bad = __ballot(chk != 0);
+#pragma unroll
+                for (int k = 0; k < LAT_W; ++k) t = t + read_lane(tau, pl[k]);
+                const uint32_t g0 = base + (uint32_t)off;
+                const bool near_limit = g0 <= STEP_LIMIT && STEP_LIMIT - g0 < (uint32_t)LAT_W;
+                if (t < T && (bad & onpath) == 0ull && !near_limit) {
+#pragma unroll
+                    for (int c = 0; c < M::NC; ++c) s.u[c] += a * S0[c] + (LAT_W - a) * S1[c];
+                    nd += (uint32_t)LAT_W;
+                    ntr += (uint32_t)LAT_W;
+                    continue;
+                }
+            }
+            // Slow path (the window that stops): lane k records the point and
+            // a of step k, and the point the step leads to.
+            t = t_in;
             int pidx = 0, pa = 0, pnext = 0;
             int L = 0, a = 0;
 #pragma unroll
@@ -317,22 +359,11 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             const int chk_next = __shfl(chk, pnext < WAVE ? pnext : 0, WAVE);
             // the time chain, the one serial part: lane k keeps the time
             // before step k; t + tau of each step is one addition, in order
-            const double t_in = t;
             double tl = t;
 #pragma unroll
             for (int k = 0; k < LAT_W; ++k) {
                 tl = lane == k ? t : tl;
                 t = t + read_lane(tp, k);
-            }
-            // the window's first state (the day's starting state or the one
-            // the previous window ended in) is checked before its first draw;
-            // the window's values above are then unused
-            const int c00 = __builtin_amdgcn_readfirstlane(chk);
-            if (c00) {
-                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
-                t = t_in;
-                done = true;
-                break;
             }
             // first step whose draw would cross the boundary, first step whose
             // transition leads to a state that fails its checks (the last
@@ -575,10 +606,10 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
         if (lane == 0) chunk = atomicAdd(&p.ctrl->work[p.group], 1u);
         chunk = __shfl(chunk, 0, WAVE);
         if (chunk >= (unsigned)p.nchunks) break;
-        // chunks [0, nbig): one heavy node per wavefront; then 64 nodes per chunk
+        // chunks [0, nbig): one heavy node per wavefront; then pack nodes per chunk
         const bool wide = (int)chunk < p.nbig;
-        const int k = wide ? (int)chunk : p.nbig + ((int)chunk - p.nbig) * WAVE + lane;
-        const bool active = k < p.n;
+        const int k = wide ? (int)chunk : p.nbig + ((int)chunk - p.nbig) * p.pack + lane;
+        const bool active = (wide || lane < p.pack) && k < p.n;
         const bool owner = active && (!wide || lane == 0);  // writes records
         Node<M> s;
         int run = 0, cur = 0, cend = 0;
@@ -655,10 +686,10 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     Tally t;
     const int lane = threadIdx.x & (WAVE - 1);
     const int gw = blockIdx.x * (blockDim.x / WAVE) + (int)(threadIdx.x / WAVE);
-    // waves [0, nbig): one heavy node per wavefront; then 64 nodes per wave
+    // waves [0, nbig): one heavy node per wavefront; then pack nodes per wave
     const bool wide = gw < p.nbig;
-    const int k = wide ? gw : p.nbig + (gw - p.nbig) * WAVE + lane;
-    const bool active = k < p.n;
+    const int k = wide ? gw : p.nbig + (gw - p.nbig) * p.pack + lane;
+    const bool active = (wide || lane < p.pack) && k < p.n;
     const bool owner = active && (!wide || lane == 0);
     Node<M> s;
     int run = 0, cur = 0, cend = 0, tcur = 0, tend = 0;

@@ -120,7 +120,10 @@ def test_other_models(lib, kind):
                                   dict(lanes=1), dict(lanes=64, wide=1), dict(lanes=64, wide=40),
                                   dict(lanes=64, wide=600, block=256), dict(lanes=64, wide=7, block=128, pipeline=2),
                                   dict(lanes=64, wide=600, lattice=2), dict(lanes=64, wide=600, mode=1, lattice=1),
-                                  dict(lanes=64, wide=90, block=64, lattice=2), dict(pipeline=2, block=128)])
+                                  dict(lanes=64, wide=90, block=64, lattice=2), dict(pipeline=2, block=128),
+                                  dict(pack=16), dict(pack=32, block=128), dict(pack=16, mode=2, lanes=1),
+                                  dict(pack=16, lanes=64, wide=40, block=256), dict(pack=32, mode=1),
+                                  dict(pack=8, lanes=64, wide=90, block=64), dict(pack=4, block=128, pipeline=2)])
 def test_launch_shape_does_not_change_bits(lib, opts):
     spec = W.config1(seed=11, Nn=600, days=50)
     ref = oracle_run(spec, 5, 0)
@@ -203,6 +206,14 @@ def test_first_error_matches_oracle(lib, case, mode):
     info = m.error_info()
     assert rc == ref["status"] != 0
     assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
+
+
+@pytest.mark.parametrize("opts", [dict(pack=2), dict(pack=48), dict(block=96), dict(lanes=2), dict(lattice=3)])
+def test_invalid_options_rejected(lib, opts):
+    spec = W.config0()
+    with pytest.raises(lib.SiminfError) as e:
+        lib.Model(spec, **opts)
+    assert e.value.code in (-1, -2)
 
 
 def test_invalid_event_rejected_at_create(lib):
@@ -354,6 +365,25 @@ def test_free_running_cases(lib, case, pipeline):
             assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), r
         else:
             _compare(m, ref, run=r, what=f"batch run {r}")
+
+
+@pytest.mark.parametrize("pack", [4, 16, 32])
+def test_packed_wavefronts_batch(lib, pack):
+    """Fewer nodes per wavefront (the rest of its lanes idle): weekly sums of
+    a batch whose runs straddle wavefronts, and the launch reports it."""
+    sets = W.ensemble_sets(seed=37, n_sets=4, replicates=2, days=60, nn_range=(20, 300))
+    batch = [(st.spec, 2) for st in sets]
+    m = lib.Model(batch, record=lib.RECORD_SUMS, pack=pack)
+    info = m.launch_info()
+    _say("packed batch", pack, info)
+    assert info["pack"] == pack
+    m.run(29, 4)
+    assert m.wait() == 0
+    sums = m.sums()
+    for r in range(m.runs):
+        spec = sets[r // 2].spec
+        ref = oracle_run(spec, 29, 4 + r)
+        assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), r
 
 
 def test_split_run_equals_full_run(lib):
