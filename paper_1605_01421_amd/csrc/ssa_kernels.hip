@@ -270,15 +270,21 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
     bool done = false;
     // blocks of LAT_BLOCK draws (lane j draws step base + j), walked in
     // windows of exactly LAT_W steps
+    const int lsrc = lk < LAT_W ? lk : 0;
     for (uint32_t base = 0; !done; base += LAT_BLOCK) {
         const StepRandoms mine = step_randoms(k0, k1, base + (uint32_t)lane, day_word, node, tag);
+        // each window's variates are fetched one window ahead
+        double e_next = __shfl(mine.e, lsrc, WAVE);
+        double r2_next = __shfl(mine.r2, lsrc, WAVE);
 #pragma unroll 1
         for (int off = 0; off < LAT_BLOCK; off += LAT_W) {
             // the pass: lane (lk, la) evaluates the state lk steps ahead with
             // la transitions of the first kind
-            const int src = off + (lk < LAT_W ? lk : 0);
-            const double e = __shfl(mine.e, src, WAVE);
-            const double r2 = __shfl(mine.r2, src, WAVE);
+            const double e = e_next;
+            const double r2 = r2_next;
+            const int nsrc = (off + LAT_W < LAT_BLOCK ? off + LAT_W : 0) + lsrc;
+            e_next = __shfl(mine.e, nsrc, WAVE);
+            r2_next = __shfl(mine.r2, nsrc, WAVE);
             int32_t uc[M::NC];
             bool neg = false;
 #pragma unroll
@@ -291,49 +297,41 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             double lam = 0.0;
             lam = lam + c0;
             lam = lam + c1;
-            const double tau = e / lam;
             const double x = lam * r2;
             const int n = (c0 > 0.0 && x <= c0) ? 0 : (c1 > 0.0 ? 1 : 0);
             // checks of the state: 1 a negative compartment, 2 a bad rate,
             // 4 lambda <= 0 (the node stops for the day)
             const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
+            // A state that fails its checks is never left by a step: its tau
+            // is taken as +inf.  A window whose path meets one then ends at
+            // t = +inf and takes the slow path below, where the failure
+            // (found one step earlier) wins over this crossing.  A state that
+            // passes has lambda > 0 and a finite tau >= 0.
+            const double tau = chk ? __builtin_inf() : e / lam;
             // The path does not depend on t: bit L of `first` says whether the
             // step from point L is of the first kind, and point (k+1, a') is
             // L + k + 1 + d.
             const unsigned long long first = __ballot(n == 0);
-            // the window's first state (the day's starting state or the one
-            // the previous window ended in) is checked before its first draw;
-            // the window's values above are then unused
-            const int c00 = __builtin_amdgcn_readfirstlane(chk);
-            if (c00) {
-                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
-                done = true;
-                break;
-            }
             // Fast path, taken by every window but the day's last: the path in
             // scalar registers, tau read from the lane of each point in turn.
-            // When every state on the path passes its checks, each tau is
-            // finite and >= 0, so the times only grow and a window that ends
-            // before T crosses nowhere.
+            // The times only grow (every tau is >= 0), so a window that ends
+            // before T neither crosses the boundary nor meets a failing state.
             const double t_in = t;
             {
                 int pl[LAT_W];
                 int L = 0, a = 0;
-                unsigned long long onpath = 0;  // path points 1 .. LAT_W-1
 #pragma unroll
                 for (int k = 0; k < LAT_W; ++k) {
                     pl[k] = L;
-                    if (k > 0) onpath |= 1ull << L;
                     const int d = (int)((first >> L) & 1ull);
                     a += d;
                     L += k + 1 + d;
                 }
-                const unsigned long long bad = __ballot(chk != 0);
 #pragma unroll
                 for (int k = 0; k < LAT_W; ++k) t = t + read_lane(tau, pl[k]);
                 const uint32_t g0 = base + (uint32_t)off;
                 const bool near_limit = g0 <= STEP_LIMIT && STEP_LIMIT - g0 < (uint32_t)LAT_W;
-                if (t < T && (bad & onpath) == 0ull && !near_limit) {
+                if (t < T && !near_limit) {
 #pragma unroll
                     for (int c = 0; c < M::NC; ++c) s.u[c] += a * S0[c] + (LAT_W - a) * S1[c];
                     nd += (uint32_t)LAT_W;
@@ -341,9 +339,18 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
                     continue;
                 }
             }
-            // Slow path (the window that stops): lane k records the point and
-            // a of step k, and the point the step leads to.
+            // Slow path (the window that stops).  The window's first state
+            // (the day's starting state or the one the previous window ended
+            // in) is checked before its first draw.
             t = t_in;
+            const int c00 = __builtin_amdgcn_readfirstlane(chk);
+            if (c00) {
+                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
+                done = true;
+                break;
+            }
+            // Lane k records the point and a of step k, and the point the
+            // step leads to.
             int pidx = 0, pa = 0, pnext = 0;
             int L = 0, a = 0;
 #pragma unroll
