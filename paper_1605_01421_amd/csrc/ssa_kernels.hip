@@ -236,6 +236,20 @@ constexpr int LAT_POINTS = LAT_W * (LAT_W + 1) / 2;
 constexpr int LAT_BLOCK = 60;
 static_assert(LAT_POINTS <= WAVE && LAT_BLOCK <= WAVE && LAT_BLOCK % LAT_W == 0, "the lattice must fit one wavefront");
 
+// The points of a window's path: pl[k + 1] = pl[k] + k + 1 + (bit pl[k] of
+// mask), each on the scalar unit as a bit test that sets SCC and an add with
+// carry of the constant k + 1 (arithmetic only; SCC is set and used inside
+// the block).
+template <int K>
+__device__ __forceinline__ void lattice_path(unsigned long long mask, int (&pl)[LAT_W + 1]) {
+    if constexpr (K < LAT_W) {
+        int r;
+        asm("s_bitcmp1_b64 %1, %2\n\ts_addc_u32 %0, %2, %3" : "=s"(r) : "s"(mask), "s"(pl[K]), "n"(K + 1) : "scc");
+        pl[K + 1] = r;
+        lattice_path<K + 1>(mask, pl);
+    }
+}
+
 // The same SSA for one heavy node on a whole wavefront, with the serial chain
 // cut to a few instructions per step.  With two transitions, the state k
 // steps ahead is u + a S[:,0] + (k - a) S[:,1] for some 0 <= a <= k.  One
@@ -259,11 +273,13 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
     const int la = lane - lk * (lk + 1) / 2;
     const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
     const uint32_t tag = stream & 0xFFFFFFu;
-    int32_t S0[M::NC], S1[M::NC];
+    int32_t S0[M::NC], S1[M::NC], Sw[M::NC], Sd[M::NC];
 #pragma unroll
     for (int c = 0; c < M::NC; ++c) {
         S0[c] = p.S[c];
         S1[c] = p.S[c + M::NC];
+        Sw[c] = LAT_W * S1[c];  // a full window with a first-kind steps moves
+        Sd[c] = S0[c] - S1[c];  // the state by Sw + a Sd
     }
     uint32_t nd = 0, ntr = 0;  // draws and transitions, wave-uniform
     int rc = 0;
@@ -318,22 +334,22 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             // before T neither crosses the boundary nor meets a failing state.
             const double t_in = t;
             {
-                int pl[LAT_W];
-                int L = 0, a = 0;
+                // point of step k; the path's last point is LAT_POINTS + a
+                // (every step k adds k + 1, and 1 more if of the first kind)
+                int pl[LAT_W + 1];
+                pl[0] = 0;
+                lattice_path<0>(first, pl);
+                const int a = pl[LAT_W] - LAT_POINTS;
+                double tv[LAT_W];
 #pragma unroll
-                for (int k = 0; k < LAT_W; ++k) {
-                    pl[k] = L;
-                    const int d = (int)((first >> L) & 1ull);
-                    a += d;
-                    L += k + 1 + d;
-                }
+                for (int k = 0; k < LAT_W; ++k) tv[k] = read_lane(tau, pl[k]);
 #pragma unroll
-                for (int k = 0; k < LAT_W; ++k) t = t + read_lane(tau, pl[k]);
+                for (int k = 0; k < LAT_W; ++k) t = t + tv[k];
                 const uint32_t g0 = base + (uint32_t)off;
                 const bool near_limit = g0 <= STEP_LIMIT && STEP_LIMIT - g0 < (uint32_t)LAT_W;
                 if (t < T && !near_limit) {
 #pragma unroll
-                    for (int c = 0; c < M::NC; ++c) s.u[c] += a * S0[c] + (LAT_W - a) * S1[c];
+                    for (int c = 0; c < M::NC; ++c) s.u[c] += Sw[c] + a * Sd[c];
                     nd += (uint32_t)LAT_W;
                     ntr += (uint32_t)LAT_W;
                     continue;
