@@ -332,8 +332,11 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
             // scalar registers, tau read from the lane of each point in turn.
             // The times only grow (every tau is >= 0), so a window that ends
             // before T neither crosses the boundary nor meets a failing state.
+            // A window that starts less than twice its expected length before
+            // T (or in a state without a positive rate) goes to the slow path
+            // at once: it most likely stops there.
             const double t_in = t;
-            {
+            if ((T - t) * read_lane(lam, 0) > 2.0 * LAT_W) {
                 // point of step k; the path's last point is LAT_POINTS + a
                 // (every step k adds k + 1, and 1 more if of the first kind)
                 int pl[LAT_W + 1];
