@@ -250,6 +250,46 @@ __device__ __forceinline__ void lattice_path(unsigned long long mask, int (&pl)[
     }
 }
 
+// What one pass of the lattice walk gives a lane: the values of the step
+// taken from its point, and the check of its state (1 a negative
+// compartment, 2 a bad rate, 4 lambda <= 0: the node stops for the day).  A
+// state that fails its checks is never left by a step, so its tau is +inf;
+// a state that passes has lambda > 0 and a finite tau >= 0.  `first` has bit
+// L set when the step from point L is of the first kind.
+struct LatticePass {
+    double tau, lam;
+    int chk;
+    unsigned long long first;
+};
+
+// Lane (lk, la) evaluates the state lk steps ahead of u with la transitions
+// of the first kind, with the variates e, r2 of step lk.
+template <class M>
+__device__ __forceinline__ LatticePass lattice_pass(const Node<M>& s, const int32_t (&u)[M::NC], int lk, int la,
+                                                    const int32_t (&S0)[M::NC], const int32_t (&S1)[M::NC],
+                                                    double e, double r2) {
+    int32_t uc[M::NC];
+    bool neg = false;
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c) {
+        uc[c] = u[c] + la * S0[c] + (lk - la) * S1[c];
+        neg |= uc[c] < 0;
+    }
+    const double c0 = M::template rate<0>(uc, s.v, s.ld, s.gd);
+    const double c1 = M::template rate<1>(uc, s.v, s.ld, s.gd);
+    LatticePass r;
+    double lam = 0.0;
+    lam = lam + c0;
+    lam = lam + c1;
+    r.lam = lam;
+    const double x = lam * r2;
+    const int n = (c0 > 0.0 && x <= c0) ? 0 : (c1 > 0.0 ? 1 : 0);
+    r.chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
+    r.tau = r.chk ? __builtin_inf() : e / lam;
+    r.first = __ballot(n == 0);
+    return r;
+}
+
 // The same SSA for one heavy node on a whole wavefront, with the serial chain
 // cut to a few instructions per step.  With two transitions, the state k
 // steps ahead is u + a S[:,0] + (k - a) S[:,1] for some 0 <= a <= k.  One
@@ -257,12 +297,14 @@ __device__ __forceinline__ void lattice_path(unsigned long long mask, int (&pl)[
 // LAT_W steps at once, all that a step computes from its state: the checks
 // of the state, the rates, lambda, tau = E_k / lambda (E_k is the
 // exponential variate of step k), and the inversion choice with r2_k.  The
-// walk then follows the realised path: per step it reads tau and the choice
-// from the lane of the current point, advances t by one addition and stops
-// at the day boundary.  Every value comes from the same operations in the
-// same order as in ssa_to_boundary, so the result is bit-identical.  Valid
-// when G marks both rates after either transition: a full recomputation
-// then equals the incremental one.
+// walk then follows the realised path: per step it reads tau from the lane
+// of the current point and advances t by one addition, and it stops at the
+// day boundary.  The path, and so the window's end state, is known before
+// the time additions: the next window's pass is computed alongside them and
+// used if the window does not stop.  Every value comes from the same
+// operations in the same order as in ssa_to_boundary, so the result is
+// bit-identical.  Valid when G marks both rates after either transition: a
+// full recomputation then equals the incremental one.
 template <class M>
 __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double t, double T, uint32_t day_word,
                                            uint32_t node, uint32_t stream, unsigned long long& transitions,
@@ -283,159 +325,143 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
     }
     uint32_t nd = 0, ntr = 0;  // draws and transitions, wave-uniform
     int rc = 0;
-    bool done = false;
-    // blocks of LAT_BLOCK draws (lane j draws step base + j), walked in
-    // windows of exactly LAT_W steps
+    // Draws come in blocks of LAT_BLOCK (lane j of the block at mb draws step
+    // mb + j); the window at draw g (a multiple of LAT_W) reads the lanes
+    // g - mb + lk of its block.
     const int lsrc = lk < LAT_W ? lk : 0;
-    for (uint32_t base = 0; !done; base += LAT_BLOCK) {
-        const StepRandoms mine = step_randoms(k0, k1, base + (uint32_t)lane, day_word, node, tag);
-        // each window's variates are fetched one window ahead
-        double e_next = __shfl(mine.e, lsrc, WAVE);
-        double r2_next = __shfl(mine.r2, lsrc, WAVE);
+    uint32_t mb = 0;
+    StepRandoms mine = step_randoms(k0, k1, (uint32_t)lane, day_word, node, tag);
+    auto ensure_block = [&](uint32_t g) {
+        if (g - mb >= (uint32_t)LAT_BLOCK) {
+            mb = g;
+            mine = step_randoms(k0, k1, g + (uint32_t)lane, day_word, node, tag);
+        }
+    };
+    LatticePass P = lattice_pass<M>(s, s.u, lk, la, S0, S1, __shfl(mine.e, lsrc, WAVE), __shfl(mine.r2, lsrc, WAVE));
 #pragma unroll 1
-        for (int off = 0; off < LAT_BLOCK; off += LAT_W) {
-            // the pass: lane (lk, la) evaluates the state lk steps ahead with
-            // la transitions of the first kind
-            const double e = e_next;
-            const double r2 = r2_next;
-            const int nsrc = (off + LAT_W < LAT_BLOCK ? off + LAT_W : 0) + lsrc;
-            e_next = __shfl(mine.e, nsrc, WAVE);
-            r2_next = __shfl(mine.r2, nsrc, WAVE);
-            int32_t uc[M::NC];
-            bool neg = false;
+    for (uint32_t g = 0;; g += LAT_W) {
+        const double t_in = t;
+        const bool near_limit = g <= STEP_LIMIT && STEP_LIMIT - g < (uint32_t)LAT_W;
+        // Fast path, taken by every window but the day's last: the path in
+        // scalar registers, tau read from the lane of each point in turn.
+        // The times only grow (every tau is >= 0), so a window that ends
+        // before T neither crosses the boundary nor meets a failing state.
+        // A window that starts less than twice its expected length before T
+        // (or in a state without a positive rate) goes to the slow path at
+        // once: it most likely stops there.
+        if (!near_limit && (T - t) * read_lane(P.lam, 0) > 2.0 * LAT_W) {
+            ensure_block(g + LAT_W);
+            const int src = (int)(g + LAT_W - mb) + lsrc;
+            const double en = __shfl(mine.e, src, WAVE);
+            const double r2n = __shfl(mine.r2, src, WAVE);
+            // point of step k; the path's last point is LAT_POINTS + a (every
+            // step k adds k + 1, and 1 more if of the first kind)
+            int pl[LAT_W + 1];
+            pl[0] = 0;
+            lattice_path<0>(P.first, pl);
+            const int a = pl[LAT_W] - LAT_POINTS;
+            int32_t un[M::NC];
 #pragma unroll
-            for (int c = 0; c < M::NC; ++c) {
-                uc[c] = s.u[c] + la * S0[c] + (lk - la) * S1[c];
-                neg |= uc[c] < 0;
-            }
-            const double c0 = M::template rate<0>(uc, s.v, s.ld, s.gd);
-            const double c1 = M::template rate<1>(uc, s.v, s.ld, s.gd);
-            double lam = 0.0;
-            lam = lam + c0;
-            lam = lam + c1;
-            const double x = lam * r2;
-            const int n = (c0 > 0.0 && x <= c0) ? 0 : (c1 > 0.0 ? 1 : 0);
-            // checks of the state: 1 a negative compartment, 2 a bad rate,
-            // 4 lambda <= 0 (the node stops for the day)
-            const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
-            // A state that fails its checks is never left by a step: its tau
-            // is taken as +inf.  A window whose path meets one then ends at
-            // t = +inf and takes the slow path below, where the failure
-            // (found one step earlier) wins over this crossing.  A state that
-            // passes has lambda > 0 and a finite tau >= 0.
-            const double tau = chk ? __builtin_inf() : e / lam;
-            // The path does not depend on t: bit L of `first` says whether the
-            // step from point L is of the first kind, and point (k+1, a') is
-            // L + k + 1 + d.
-            const unsigned long long first = __ballot(n == 0);
-            // Fast path, taken by every window but the day's last: the path in
-            // scalar registers, tau read from the lane of each point in turn.
-            // The times only grow (every tau is >= 0), so a window that ends
-            // before T neither crosses the boundary nor meets a failing state.
-            // A window that starts less than twice its expected length before
-            // T (or in a state without a positive rate) goes to the slow path
-            // at once: it most likely stops there.
-            const double t_in = t;
-            if ((T - t) * read_lane(lam, 0) > 2.0 * LAT_W) {
-                // point of step k; the path's last point is LAT_POINTS + a
-                // (every step k adds k + 1, and 1 more if of the first kind)
-                int pl[LAT_W + 1];
-                pl[0] = 0;
-                lattice_path<0>(first, pl);
-                const int a = pl[LAT_W] - LAT_POINTS;
-                double tv[LAT_W];
+            for (int c = 0; c < M::NC; ++c) un[c] = s.u[c] + Sw[c] + a * Sd[c];
+            // the next window's pass, from the state this one ends in
+            const LatticePass Pn = lattice_pass<M>(s, un, lk, la, S0, S1, en, r2n);
+            double tv[LAT_W];
 #pragma unroll
-                for (int k = 0; k < LAT_W; ++k) tv[k] = read_lane(tau, pl[k]);
+            for (int k = 0; k < LAT_W; ++k) tv[k] = read_lane(P.tau, pl[k]);
 #pragma unroll
-                for (int k = 0; k < LAT_W; ++k) t = t + tv[k];
-                const uint32_t g0 = base + (uint32_t)off;
-                const bool near_limit = g0 <= STEP_LIMIT && STEP_LIMIT - g0 < (uint32_t)LAT_W;
-                if (t < T && !near_limit) {
+            for (int k = 0; k < LAT_W; ++k) t = t + tv[k];
+            // the next pass is needed only if the window goes through; this
+            // empty statement makes it be computed here, beside the time
+            // additions, rather than after the test (no instruction)
+            asm volatile("" ::"v"(Pn.tau), "v"(Pn.lam), "v"(Pn.chk));
+            if (t < T) {
 #pragma unroll
-                    for (int c = 0; c < M::NC; ++c) s.u[c] += Sw[c] + a * Sd[c];
-                    nd += (uint32_t)LAT_W;
-                    ntr += (uint32_t)LAT_W;
-                    continue;
-                }
-            }
-            // Slow path (the window that stops).  The window's first state
-            // (the day's starting state or the one the previous window ended
-            // in) is checked before its first draw.
-            t = t_in;
-            const int c00 = __builtin_amdgcn_readfirstlane(chk);
-            if (c00) {
-                rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
-                done = true;
-                break;
-            }
-            // Lane k records the point and a of step k, and the point the
-            // step leads to.
-            int pidx = 0, pa = 0, pnext = 0;
-            int L = 0, a = 0;
-#pragma unroll
-            for (int k = 0; k < LAT_W; ++k) {
-                pidx = lane == k ? L : pidx;
-                pa = lane == k ? a : pa;
-                const int d = (int)((first >> L) & 1ull);
-                a += d;
-                L += k + 1 + d;
-                pnext = lane == k ? L : pnext;
-            }
-            const double tp = __shfl(tau, pidx, WAVE);
-            const int chk_next = __shfl(chk, pnext < WAVE ? pnext : 0, WAVE);
-            // the time chain, the one serial part: lane k keeps the time
-            // before step k; t + tau of each step is one addition, in order
-            double tl = t;
-#pragma unroll
-            for (int k = 0; k < LAT_W; ++k) {
-                tl = lane == k ? t : tl;
-                t = t + read_lane(tp, k);
-            }
-            // first step whose draw would cross the boundary, first step whose
-            // transition leads to a state that fails its checks (the last
-            // step's successor is checked by the next window), and the step
-            // whose draw would exceed the step limit
-            const unsigned long long cross = __ballot(lane < LAT_W && tl + tp >= T);
-            const unsigned long long fail = __ballot(lane + 1 < LAT_W && chk_next != 0);
-            const int kc = cross ? __builtin_ctzll(cross) : WAVE;
-            const int kf = fail ? __builtin_ctzll(fail) : WAVE;
-            const uint32_t g = base + (uint32_t)off;
-            const int kl = g <= STEP_LIMIT && STEP_LIMIT - g < (uint32_t)LAT_W ? (int)(STEP_LIMIT - g) : WAVE;
-            int kend, aend;
-            if (kl < LAT_W && kl <= kc && kl <= kf) {
-                // the draw with index STEP_LIMIT: the node's rates are unusable
-                kend = kl;
-                aend = __builtin_amdgcn_readlane(pa, kl);
-                nd += (uint32_t)kl;
-                ntr += (uint32_t)kl;
-                rc = E_BAD_RATE;
-                done = true;
-            } else if (kc <= kf && kc < LAT_W) {
-                // stops at the boundary before the transition of step kc
-                kend = kc;
-                aend = __builtin_amdgcn_readlane(pa, kc);
-                nd += (uint32_t)kc + 1u;
-                ntr += (uint32_t)kc;
-                done = true;
-            } else if (kf < LAT_W) {
-                // the transition of step kf leads to a failing state
-                kend = kf + 1;
-                aend = __builtin_amdgcn_readlane(pa, kf + 1);
-                const int code = __builtin_amdgcn_readlane(chk_next, kf);
-                rc = (code & 1) ? E_NEG_STATE : (code & 2) ? E_BAD_RATE : 0;
-                nd += (uint32_t)kf + 1u;
-                ntr += (uint32_t)kf + 1u;
-                done = true;
-            } else {
-                kend = LAT_W;
-                aend = a;
+                for (int c = 0; c < M::NC; ++c) s.u[c] = un[c];
                 nd += (uint32_t)LAT_W;
                 ntr += (uint32_t)LAT_W;
+                P = Pn;
+                continue;
             }
-#pragma unroll
-            for (int c = 0; c < M::NC; ++c) s.u[c] += aend * S0[c] + (kend - aend) * S1[c];
-            if (done) break;
+            t = t_in;
         }
+        // Slow path (the window that stops).  The window's first state (the
+        // day's starting state or the one the previous window ended in) is
+        // checked before its first draw.
+        const int c00 = __builtin_amdgcn_readfirstlane(P.chk);
+        if (c00) {
+            rc = (c00 & 1) ? E_NEG_STATE : (c00 & 2) ? E_BAD_RATE : 0;
+            break;
+        }
+        // Lane k records the point and a of step k, and the point the step
+        // leads to.
+        int pidx = 0, pa = 0, pnext = 0;
+        int L = 0, a = 0;
+#pragma unroll
+        for (int k = 0; k < LAT_W; ++k) {
+            pidx = lane == k ? L : pidx;
+            pa = lane == k ? a : pa;
+            const int d = (int)((P.first >> L) & 1ull);
+            a += d;
+            L += k + 1 + d;
+            pnext = lane == k ? L : pnext;
+        }
+        const double tp = __shfl(P.tau, pidx, WAVE);
+        const int chk_next = __shfl(P.chk, pnext < WAVE ? pnext : 0, WAVE);
+        // the time chain: lane k keeps the time before step k; t + tau of
+        // each step is one addition, in order
+        double tl = t;
+#pragma unroll
+        for (int k = 0; k < LAT_W; ++k) {
+            tl = lane == k ? t : tl;
+            t = t + read_lane(tp, k);
+        }
+        // first step whose draw would cross the boundary, first step whose
+        // transition leads to a state that fails its checks (the last step's
+        // successor is checked by the next window), and the step whose draw
+        // would exceed the step limit.  A failing state's tau of +inf can add
+        // a crossing one step after the failure, which the failure precedes.
+        const unsigned long long cross = __ballot(lane < LAT_W && tl + tp >= T);
+        const unsigned long long fail = __ballot(lane + 1 < LAT_W && chk_next != 0);
+        const int kc = cross ? __builtin_ctzll(cross) : WAVE;
+        const int kf = fail ? __builtin_ctzll(fail) : WAVE;
+        const int kl = near_limit ? (int)(STEP_LIMIT - g) : WAVE;
+        int kend, aend;
+        bool done = true;
+        if (kl < LAT_W && kl <= kc && kl <= kf) {
+            // the draw with index STEP_LIMIT: the node's rates are unusable
+            kend = kl;
+            aend = __builtin_amdgcn_readlane(pa, kl);
+            nd += (uint32_t)kl;
+            ntr += (uint32_t)kl;
+            rc = E_BAD_RATE;
+        } else if (kc <= kf && kc < LAT_W) {
+            // stops at the boundary before the transition of step kc
+            kend = kc;
+            aend = __builtin_amdgcn_readlane(pa, kc);
+            nd += (uint32_t)kc + 1u;
+            ntr += (uint32_t)kc;
+        } else if (kf < LAT_W) {
+            // the transition of step kf leads to a failing state
+            kend = kf + 1;
+            aend = __builtin_amdgcn_readlane(pa, kf + 1);
+            const int code = __builtin_amdgcn_readlane(chk_next, kf);
+            rc = (code & 1) ? E_NEG_STATE : (code & 2) ? E_BAD_RATE : 0;
+            nd += (uint32_t)kf + 1u;
+            ntr += (uint32_t)kf + 1u;
+        } else {
+            kend = LAT_W;
+            aend = a;
+            nd += (uint32_t)LAT_W;
+            ntr += (uint32_t)LAT_W;
+            done = false;
+        }
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) s.u[c] += aend * S0[c] + (kend - aend) * S1[c];
+        if (done) break;
+        // the window ran through: the next one's pass
+        ensure_block(g + LAT_W);
+        const int src = (int)(g + LAT_W - mb) + lsrc;
+        P = lattice_pass<M>(s, s.u, lk, la, S0, S1, __shfl(mine.e, src, WAVE), __shfl(mine.r2, src, WAVE));
     }
     if (lane == 0) {
         draws += nd;
