@@ -730,6 +730,28 @@ __device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long
     }
 }
 
+// Workgroups are handed to the device's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  One-lane-per-node wavefronts store
+// a day's record of a compartment as pack consecutive 4-byte words, less
+// than a 128-byte cache line when pack < 32; neighbouring wavefronts on
+// different XCDs would then write parts of one line from several L2s.  From
+// the first whole round of XCDs after the wide nodes' workgroups (a, a
+// multiple of 8) on, workgroups are renumbered in spans of 8 g: XCD x takes
+// g consecutive ones, which together fill whole lines, while the spans still
+// rotate over all XCDs (neighbouring chunks have similar work: the nodes are
+// ordered by it).  A bijection: workgroups outside whole spans keep their
+// number.
+constexpr int XCDS = 8;
+__device__ __forceinline__ int xcd_block(int b, int b0, int nblk, int g) {
+    const int a = (b0 + XCDS - 1) / XCDS * XCDS;
+    const int span = XCDS * g;
+    const int full_end = nblk > a ? a + (nblk - a) / span * span : a;
+    if (g <= 1 || b < a || b >= full_end) return b;
+    const int r = b - a;
+    const int rem = r % span;
+    return a + (r - rem) + (rem % XCDS) * g + rem / XCDS;
+}
+
 template <class M, bool PIPE>
 __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     KParams p = pa;
@@ -737,7 +759,10 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     p.stream_base = pa.rp->stream_base;
     Tally t;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int gw = blockIdx.x * (blockDim.x / WAVE) + (int)(threadIdx.x / WAVE);
+    const int wpb = blockDim.x / WAVE;
+    const int line_g = 32 / (p.pack * wpb);  // workgroups whose records fill one 128-byte line
+    const int gw = xcd_block(blockIdx.x, (p.nbig + wpb - 1) / wpb, gridDim.x, line_g) * wpb +
+                   (int)(threadIdx.x / WAVE);
     // waves [0, nbig): one heavy node per wavefront; then pack nodes per wave
     const bool wide = gw < p.nbig;
     const int k = wide ? gw : p.nbig + (gw - p.nbig) * p.pack + lane;
