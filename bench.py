@@ -249,6 +249,8 @@ def main():
     ap.add_argument("--wide", type=int, default=0, help="with --lanes 64: wavefront-wide nodes")
     ap.add_argument("--pipeline", type=int, default=0, help="0 auto, 1 on, 2 off")
     ap.add_argument("--pack", type=int, default=0, help="nodes per one-lane-per-node wavefront: 0 auto, 4, 8, 16, 32, 64")
+    ap.add_argument("--group", type=int, default=0,
+                    help="nodes after the wide ones on a group of 16 lanes: 0 none/tuned, -1 all, N")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the run from a captured HIP graph: 1 on, 0 off, -1 on for batches without transfers")
     ap.add_argument("--no-cpu", action="store_true")
@@ -277,7 +279,7 @@ def main():
     graph = args.graph if args.graph >= 0 else int(batch)
     model = siminf.Model(spec, record=siminf.RECORD_SUMS if batch else siminf.RECORD_FULL, block=args.block,
                          order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline,
-                         pack=args.pack, graph=graph)
+                         pack=args.pack, graph=graph, group=args.group)
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
@@ -340,7 +342,8 @@ def main():
         "data": "synthetic",
         "config": dict(desc, seed=seed0, block=info["block"], blocks=info["blocks"],
                        kernel=["free-running", "grid-barrier", "dataflow"][info["mode"]],
-                       wide_nodes=info["wide"], pipeline=info["pipeline"], pack=info["pack"], graph=graph),
+                       wide_nodes=info["wide"], pipeline=info["pipeline"], pack=info["pack"],
+                       group_nodes=info["group"], graph=graph),
         "transitions_per_s": transitions / wall,
         "events_per_step": events / args.steps,
         "kernel_ms_mean": mean_kernel_s * 1e3,

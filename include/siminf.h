@@ -162,6 +162,13 @@ typedef struct {
                           wavefront) when the device has SIMDs to spare.  The
                           grid-barrier kernel always packs 64; the results do
                           not depend on it. */
+    int32_t group;     /* how many nodes after the wavefront-wide ones get a
+                          group of 16 lanes each (4 nodes a wavefront), on
+                          which the lattice walk covers 5 steps per pass: 0
+                          none (the autotuner may choose some), -1 all, else
+                          that many.  Only where the lattice walk applies (see
+                          lattice) and not in the grid-barrier kernel; the
+                          results do not depend on it. */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;
@@ -227,8 +234,9 @@ int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32
  * out[0] threads per block, out[1] blocks, out[2] kernel (0 free-running,
  * 1 grid-barrier, 2 dataflow), out[3] pipelining on/off, out[4] order,
  * out[5] nodes carried by a whole wavefront, out[6] nodes per wavefront of
- * the others (the pack option). */
-int siminf_launch_info(const siminf_model *m, int32_t out[7]);
+ * the one-lane-per-node ones (the pack option), out[7] nodes on a group of
+ * lanes (the group option). */
+int siminf_launch_info(const siminf_model *m, int32_t out[8]);
 
 /* Autotuner: runs the model `repeats` times for each candidate launch shape
  * (threads per block 64/128/256; no wavefront-wide nodes, or those whose
@@ -238,7 +246,10 @@ int siminf_launch_info(const siminf_model *m, int32_t out[7]);
  * two repeats; written to *best_ms if not NULL).  With pack = 0 and fewer
  * nodes than the device has SIMDs times 64, it then tries 32, 16, 8 and 4
  * nodes per wavefront on the best shape and, if one of those wins, the four
- * wide-node choices again with it.  Every shape gives bit-identical results;
+ * wide-node choices again with it; then (with group = 0) groups of lanes for
+ * the heaviest eighth, quarter or half of the nodes after the wide ones, or
+ * for all of them, each with the packing chosen so far and with 16 and 8
+ * nodes per one-lane wavefront.  Every shape gives bit-identical results;
  * the handle's recorded results are overwritten.  With the environment
  * variable SIMINF_AUTOTUNE_LOG set (and not "0"), each candidate's time is
  * printed to stderr as it is measured. */

@@ -9,6 +9,7 @@ namespace siminf {
 constexpr int MAX_NC = 4;     // largest compartment count of the built-in models
 constexpr int MAX_NT = 2;     // every built-in model has two transitions
 constexpr int WAVE = 64;      // gfx950 wavefront
+constexpr int GROUP_LANES = 16;  // lanes of a node carried by a group (4 groups a wavefront)
 constexpr int MAX_GROUPS = 8; // one group per built-in model present in a batch
 
 // phases of one unit of time, in the order of Appendix A
@@ -69,14 +70,15 @@ struct EventSoA {
 };
 
 // Position of record m, component c (of width components) of node k in a
-// trajectory buffer of ntspan records of n nodes.  The first nbig nodes, each
-// carried by a whole wavefront, are stored node-major so that one node's
-// consecutive records fill the same cache lines from one wavefront; the
-// others are stored component-major per record, so that the 64 nodes of a
-// wavefront store contiguous runs.
-__host__ __device__ inline size_t rec_index(int m, int c, int k, int width, int ntspan, int n, int nbig) {
-    if (k < nbig) return ((size_t)k * ntspan + m) * width + c;
-    return (size_t)nbig * ntspan * width + ((size_t)m * width + c) * (size_t)(n - nbig) + (size_t)(k - nbig);
+// trajectory buffer of ntspan records of n nodes.  The first nmajor nodes,
+// each carried by a whole wavefront or a group of lanes, are stored
+// node-major so that one node's consecutive records fill the same cache
+// lines from one wavefront; the others are stored component-major per
+// record, so that the nodes of a wavefront store contiguous runs.
+__host__ __device__ inline size_t rec_index(int m, int c, int k, int width, int ntspan, int n, int nmajor) {
+    if (k < nmajor) return ((size_t)k * ntspan + m) * width + c;
+    return (size_t)nmajor * ntspan * width + ((size_t)m * width + c) * (size_t)(n - nmajor) +
+           (size_t)(k - nmajor);
 }
 
 struct KParams {
@@ -128,6 +130,9 @@ struct KParams {
     int32_t nblocks;
     int32_t pipeline;            // 1: overlap the next step's random numbers with this step
     int32_t nbig;                // the first nbig nodes each get a whole wavefront
+    int32_t ngrp;                // the next ngrp nodes get a group of lanes each (the
+    int32_t ngw;                 //   lattice walk on a group), ngw wavefronts of them
+    int32_t nmajor;              // nbig + ngrp: nodes whose records are node-major
     int32_t lattice;             // wide nodes walk a lattice of reachable states
     uint64_t wait_ticks;         // wall-clock ticks one wait may last before abort
     const RunParams* rp;         // seed and stream base of the current run (device)
@@ -138,8 +143,8 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st);
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem,
                         hipStream_t st);
-int max_blocks_per_cu(int model, int mode, int pipeline, int block, size_t shmem);
-hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nbig,
+int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem);
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nmajor,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
 hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,
                              int case_c, uint32_t mask, int reps, int k0, int nk,

@@ -211,10 +211,18 @@ int default_wide(const siminf_model* m, const Group& g, int div = 16) {
     return nb;
 }
 
+// The first 1/div of the nodes after the nbig wide ones (none for div <= 0):
+// in the binned order, the heaviest of them, candidates for a group of
+// lanes each.
+int default_group(const Group& g, int nbig, int div) {
+    if (div <= 0 || nbig >= g.n) return 0;
+    return (g.n - nbig + div - 1) / div;
+}
+
 // Kernel and launch shape of one group.  want_mode applies to groups with
 // external transfers: 0 auto (dataflow if every node wavefront and the worker
 // fit on the device at once, else grid barrier), 1 barrier, 2 dataflow.
-int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode, int pack) {
+int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode, int pack, int ngrp) {
     drop_graph(m);
     KParams& p = g.p;
     const int n = g.n;
@@ -222,6 +230,9 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     if (cus <= 0) return SIMINF_E_DEVICE;
     nbig = std::max(0, std::min(nbig, n));
     if (pack != 4 && pack != 8 && pack != 16 && pack != 32) pack = WAVE;
+    // nodes on a group of lanes: only where the lattice walk applies
+    const int per_grp = WAVE / GROUP_LANES;
+    ngrp = p.lattice ? std::max(0, std::min(ngrp, n - nbig)) : 0;
     // pipelining pays where lanes are scarce (latency-bound runs); with many
     // waves per SIMD the extra, unused last draw of each node-day only costs
     const int simd_lanes = cus * 4 * WAVE;
@@ -232,14 +243,23 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     size_t shmem = 0;
     if (g.n_e2 > 0) {
         if (want_mode == 0 || want_mode == 2) {
-            const int per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, block, 0);
             int nb = nbig;
-            auto need = [&](int k) { return (k + (n - k + pack - 1) / pack + wpb - 1) / wpb; };
-            while (nb > 0 && per_cu > 0 && need(nb) > per_cu * cus) nb /= 2;
-            if (per_cu > 0 && need(nb) <= per_cu * cus) {
+            int ng = std::min(ngrp, n - nb);
+            int per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, ng > 0, block, 0);
+            auto need = [&](int k, int gn) {
+                return (k + (gn + per_grp - 1) / per_grp + (n - k - gn + pack - 1) / pack + wpb - 1) / wpb;
+            };
+            // every wavefront must be resident: drop the groups first, then halve the wide nodes
+            if (ng > 0 && (per_cu <= 0 || need(nb, ng) > per_cu * cus)) {
+                ng = 0;
+                per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, false, block, 0);
+            }
+            while (nb > 0 && per_cu > 0 && need(nb, ng) > per_cu * cus) nb /= 2;
+            if (per_cu > 0 && need(nb, std::min(ng, n - nb)) <= per_cu * cus) {
                 mode = MODE_FLOW;
                 nbig = nb;
-                blocks = std::max(1, need(nb));
+                ngrp = std::min(ng, n - nb);
+                blocks = std::max(1, need(nb, ngrp));
             } else if (want_mode == 2) {
                 return SIMINF_E_UNSUPPORTED;
             }
@@ -248,16 +268,17 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
             mode = MODE_BARRIER;
             shmem = 0;
             nbig = 0;
+            ngrp = 0;
             pack = WAVE;  // the barrier kernel strides over nodes 64 to a wavefront
-            const int per_cu = max_blocks_per_cu(g.model, MODE_BARRIER, p.pipeline, block, 0);
+            const int per_cu = max_blocks_per_cu(g.model, MODE_BARRIER, p.pipeline, false, block, 0);
             if (per_cu <= 0) return SIMINF_E_DEVICE;
             blocks = std::max(1, std::min(per_cu * cus, (n + block - 1) / block));
             if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
         }
     } else {
-        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, p.pipeline, block, 0);
+        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, p.pipeline, ngrp > 0, block, 0);
         if (per_cu <= 0) return SIMINF_E_DEVICE;
-        const int chunks = nbig + (n - nbig + pack - 1) / pack;
+        const int chunks = nbig + (ngrp + per_grp - 1) / per_grp + (n - nbig - ngrp + pack - 1) / pack;
         blocks = std::max(1, std::min(per_cu * cus, (chunks + wpb - 1) / wpb));
         if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
     }
@@ -265,7 +286,10 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     p.mode = mode;
     p.nbig = nbig;
     p.pack = pack;
-    p.nchunks = nbig + (n - nbig + pack - 1) / pack;
+    p.ngrp = ngrp;
+    p.ngw = (ngrp + per_grp - 1) / per_grp;
+    p.nmajor = nbig + ngrp;
+    p.nchunks = nbig + p.ngw + (n - nbig - ngrp + pack - 1) / pack;
     g.block = block;
     g.blocks = blocks;
     g.shmem = shmem;
@@ -295,8 +319,9 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
-    if (m->opt.pack != 0 && m->opt.pack != 4 && m->opt.pack != 8 && m->opt.pack != 16 && m->opt.pack != 32 &&
-        m->opt.pack != 64) {
+    if ((m->opt.pack != 0 && m->opt.pack != 4 && m->opt.pack != 8 && m->opt.pack != 16 && m->opt.pack != 32 &&
+         m->opt.pack != 64) ||
+        m->opt.group < -1) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -762,7 +787,9 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 alloc_device(m->owned, (size_t)p.n_e2 * MAX_NC, &p.mail_big))
                 return hip_fail(m);
         }
-        const int rc = configure(m, g, m->opt.block, default_wide(m, g), m->opt.pipeline, m->opt.mode, m->opt.pack);
+        const int nb = default_wide(m, g);
+        const int rc = configure(m, g, m->opt.block, nb, m->opt.pipeline, m->opt.mode, m->opt.pack,
+                                 m->opt.group < 0 ? g.n : m->opt.group);
         if (rc) {
             set_create_error(m, rc, -1, -1);
             return rc;
@@ -951,7 +978,7 @@ int siminf_trajectory(siminf_model* m, int32_t run, int32_t* U, double* V, int32
         } else tmpV = true;
     }
     int rc = SIMINF_OK;
-    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, g.p.nbig, m->d_pos + ri.noff, ri.nn, dU, dV, nullptr) !=
+    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, g.p.nmajor, m->d_pos + ri.noff, ri.nn, dU, dV, nullptr) !=
             hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         rc = SIMINF_E_DEVICE;
@@ -1004,10 +1031,10 @@ int siminf_error_info(const siminf_model* m, int32_t* code, int64_t* step, int32
     return SIMINF_OK;
 }
 
-int siminf_launch_info(const siminf_model* m, int32_t out[7]) {
+int siminf_launch_info(const siminf_model* m, int32_t out[8]) {
     if (!m || !out) return SIMINF_E_ARG;
     if (m->groups.empty()) {
-        for (int i = 0; i < 7; ++i) out[i] = 0;
+        for (int i = 0; i < 8; ++i) out[i] = 0;
         return SIMINF_OK;
     }
     const Group& g = m->groups[0];
@@ -1018,6 +1045,7 @@ int siminf_launch_info(const siminf_model* m, int32_t out[7]) {
     out[4] = m->opt.order;
     out[5] = g.p.nbig;
     out[6] = g.p.pack;
+    out[7] = g.p.ngrp;
     return SIMINF_OK;
 }
 
@@ -1026,14 +1054,20 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     if (m->groups.empty()) return SIMINF_OK;
     finish(m);
     struct Cand {
-        int block, wide_div, pipeline, pack;
+        int block, wide_div, pipeline, pack, grp_div;  // grp_div: see default_group (-1: none)
+    };
+    auto groups_of = [&](const Group& g, int nb, int gdiv) {
+        if (m->opt.group != 0) return m->opt.group < 0 ? g.n : (int)m->opt.group;
+        return m->opt.order == 1 ? 0 : default_group(g, nb, gdiv);
     };
     // lower-median SSA-kernel time of one candidate over `repeats` runs, or a
     // negative value if it cannot be launched
     auto measure = [&](const Cand& c) -> double {
         for (Group& g : m->groups) {
             const int nb = default_wide(m, g, c.wide_div);
-            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode, c.pack) != SIMINF_OK) return -1.0;
+            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode, c.pack, groups_of(g, nb, c.grp_div)) !=
+                SIMINF_OK)
+                return -1.0;
         }
         std::vector<double> t;
         for (int r = 0; r < repeats; ++r) {
@@ -1050,7 +1084,7 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     std::vector<Cand> cands;
     for (int block : {64, 128, 256})
         for (int div : {0, 4, 16, 64})  // wide nodes: none, or work above 1/div of the heaviest
-            for (int pipe : {1, 2}) cands.push_back({block, div, pipe, pack0});
+            for (int pipe : {1, 2}) cands.push_back({block, div, pipe, pack0, -1});
     double best = 1e300;
     Cand pick = cands[0];
     bool any = false;
@@ -1059,8 +1093,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     auto consider = [&](const Cand& c) {
         const double t = measure(c);
         if (log) {
-            std::fprintf(stderr, "siminf_autotune: block %d wide_div %d pipeline %d pack %d: %.3f ms\n", c.block,
-                         c.wide_div, c.pipeline, c.pack, t);
+            std::fprintf(stderr, "siminf_autotune: block %d wide_div %d pipeline %d pack %d group_div %d: %.3f ms\n",
+                         c.block, c.wide_div, c.pipeline, c.pack, c.grp_div, t);
             std::fflush(stderr);
         }
         if (t >= 0.0 && t < best) {
@@ -1080,15 +1114,30 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     for (const Group& g : m->groups) lanes_needed += g.n;
     if (m->opt.pack == 0 && (lanes_needed + WAVE - 1) / WAVE < (long long)device_cus(m) * 4) {
         const Cand first = pick;
-        for (int pack : {32, 16, 8, 4}) consider({first.block, first.wide_div, first.pipeline, pack});
+        for (int pack : {32, 16, 8, 4}) consider({first.block, first.wide_div, first.pipeline, pack, -1});
         if (pick.pack != first.pack) {
             const Cand second = pick;
             for (int div : {0, 4, 16, 64})
-                if (div != second.wide_div) consider({second.block, div, second.pipeline, second.pack});
+                if (div != second.wide_div) consider({second.block, div, second.pipeline, second.pack, -1});
+        }
+        // then the heaviest nodes after the wide ones on groups of lanes (the
+        // lattice walk on GROUP_LANES lanes): an eighth, a quarter, half or
+        // all of them, with the packing chosen so far or 16 or 8 nodes per
+        // one-lane wavefront (groups take more wavefronts, and a launch whose
+        // wavefronts cannot all be resident drops them)
+        if (m->opt.group == 0 && m->opt.order != 1) {
+            const Cand third = pick;
+            std::vector<int> packs{third.pack};
+            if (m->opt.pack == 0)
+                for (int pk : {16, 8})
+                    if (pk != third.pack) packs.push_back(pk);
+            for (int pack : packs)
+                for (int gdiv : {8, 4, 2, 1}) consider({third.block, third.wide_div, third.pipeline, pack, gdiv});
         }
     }
     for (Group& g : m->groups) {
-        configure(m, g, pick.block, default_wide(m, g, pick.wide_div), pick.pipeline, m->opt.mode, pick.pack);
+        const int nb = default_wide(m, g, pick.wide_div);
+        configure(m, g, pick.block, nb, pick.pipeline, m->opt.mode, pick.pack, groups_of(g, nb, pick.grp_div));
     }
     if (best_ms) *best_ms = best;
     return SIMINF_OK;

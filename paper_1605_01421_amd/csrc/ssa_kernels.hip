@@ -470,6 +470,136 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
     return rc;
 }
 
+// The lattice walk for a node carried by GRP_LANES lanes (a group; a
+// wavefront holds WAVE / GRP_LANES of them, each on its own node).  Lane
+// (lk, la) of a group evaluates the state lk steps ahead with la transitions
+// of the first kind, for the next GRP_W steps (GRP_POINTS lanes; the last
+// lane of the group idles in the pass).  The group's lanes draw GRP_BLOCK
+// steps' random numbers at once (lane j draws step base + j).  The path is
+// read from the group's bits of one ballot; tau and the check of each point
+// on it are then gathered and the steps are walked in order, each lane of
+// the group doing the same (group-uniform) work, with exactly the checks and
+// counts of ssa_to_boundary.  Must be called by every lane of the wavefront
+// (it shuffles and ballots); `live` marks the groups whose node steps.
+constexpr int GRP_LANES = GROUP_LANES;
+constexpr int GRP_W = 5;
+constexpr int GRP_POINTS = GRP_W * (GRP_W + 1) / 2;
+constexpr int GRP_BLOCK = 15;
+static_assert(GRP_POINTS < GRP_LANES && GRP_BLOCK <= GRP_LANES && GRP_BLOCK % GRP_W == 0 && WAVE % GRP_LANES == 0,
+              "a group's lattice must fit its lanes");
+
+template <class M>
+__device__ __forceinline__ int ssa_group(const KParams& p, Node<M>& s, bool live, double t, double T,
+                                         uint32_t day_word, uint32_t node, uint32_t stream,
+                                         unsigned long long& transitions, unsigned long long& draws) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int gl = lane % GRP_LANES;
+    const int gb = lane - gl;  // the group's first lane
+    int lk = 0;
+    while (lk < GRP_W - 1 && (lk + 1) * (lk + 2) / 2 <= gl) ++lk;
+    const int la = gl < GRP_POINTS ? gl - lk * (lk + 1) / 2 : 0;
+    const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
+    const uint32_t tag = stream & 0xFFFFFFu;
+    int32_t S0[M::NC], S1[M::NC];
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c) {
+        S0[c] = p.S[c];
+        S1[c] = p.S[c + M::NC];
+    }
+    unsigned long long nd = 0, ntr = 0;  // group-uniform
+    int rc = 0;
+    bool done = !live;
+    uint32_t g = 0, mb = 0;
+    StepRandoms mine = step_randoms(k0, k1, (uint32_t)gl, day_word, node, tag);
+    while (__any(!done)) {
+        // refill the group's block when this window's draws leave it (the
+        // groups still walking all sit at the same draw g)
+        const bool refill = !done && g + GRP_W - mb > (uint32_t)GRP_BLOCK;
+        if (__any(refill)) {
+            if (refill) {
+                mb = g;
+                mine = step_randoms(k0, k1, g + (uint32_t)gl, day_word, node, tag);
+            }
+        }
+        const int src = gb + (done ? 0 : (int)(g - mb)) + lk;
+        const double e = __shfl(mine.e, src, WAVE);
+        const double r2 = __shfl(mine.r2, src, WAVE);
+        // the pass (as in lattice_pass, per group)
+        int32_t uc[M::NC];
+        bool neg = false;
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) {
+            uc[c] = s.u[c] + la * S0[c] + (lk - la) * S1[c];
+            neg |= uc[c] < 0;
+        }
+        const double c0 = M::template rate<0>(uc, s.v, s.ld, s.gd);
+        const double c1 = M::template rate<1>(uc, s.v, s.ld, s.gd);
+        double lam = 0.0;
+        lam = lam + c0;
+        lam = lam + c1;
+        const double x = lam * r2;
+        const int n = (c0 > 0.0 && x <= c0) ? 0 : (c1 > 0.0 ? 1 : 0);
+        const int chk = neg ? 1 : !(rate_ok(c0) && rate_ok(c1)) ? 2 : !(lam > 0.0) ? 4 : 0;
+        const double tau = chk ? 0.0 : e / lam;
+        const unsigned long long first = __ballot(n == 0);
+        const uint32_t mask = (uint32_t)(first >> gb) & ((1u << GRP_POINTS) - 1u);
+        // the path: point of step k, and whether that step is of the first kind
+        int pl[GRP_W], pd[GRP_W];
+        int L = 0;
+#pragma unroll
+        for (int k = 0; k < GRP_W; ++k) {
+            pl[k] = L;
+            pd[k] = (int)((mask >> L) & 1u);
+            L += k + 1 + pd[k];
+        }
+        double tk[GRP_W];
+        int ck[GRP_W];
+#pragma unroll
+        for (int k = 0; k < GRP_W; ++k) {
+            tk[k] = __shfl(tau, gb + pl[k], WAVE);
+            ck[k] = __shfl(chk, gb + pl[k], WAVE);
+        }
+        // the steps in order: the state's checks, the step limit, the draw,
+        // the day boundary, the transition
+        int kapp = 0, aapp = 0;  // transitions applied in this window, of the first kind
+        bool stop = done;
+#pragma unroll
+        for (int k = 0; k < GRP_W; ++k) {
+            if (!stop) {
+                if (ck[k]) {
+                    rc = (ck[k] & 1) ? E_NEG_STATE : (ck[k] & 2) ? E_BAD_RATE : 0;
+                    stop = true;
+                } else if (g + (uint32_t)k == STEP_LIMIT) {
+                    rc = E_BAD_RATE;
+                    stop = true;
+                } else {
+                    nd += 1;
+                    const double tn = t + tk[k];
+                    if (tn >= T) {
+                        stop = true;
+                    } else {
+                        t = tn;
+                        ntr += 1;
+                        kapp += 1;
+                        aapp += pd[k];
+                    }
+                }
+            }
+        }
+        if (!done) {
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) s.u[c] += aapp * S0[c] + (kapp - aapp) * S1[c];
+            done = stop;
+            g += (uint32_t)GRP_W;
+        }
+    }
+    if (gl == 0) {
+        draws += nd;
+        transitions += ntr;
+    }
+    return rc;
+}
+
 // One scheduled event (section 3.3) from its packed record, on node state u
 // (and destination ud for an external transfer).  Indices were validated
 // when the model was created.  Returns 0 or E_OVERDRAW (state unchanged).
@@ -550,9 +680,9 @@ __device__ __forceinline__ void record(const KParams& p, const Node<M>& s, int k
         if (p.record == 0) {
             if (active) {
 #pragma unroll
-                for (int c = 0; c < M::NC; ++c) p.U[rec_index(m, c, k, M::NC, p.ntspan, p.n, p.nbig)] = s.u[c];
+                for (int c = 0; c < M::NC; ++c) p.U[rec_index(m, c, k, M::NC, p.ntspan, p.n, p.nmajor)] = s.u[c];
 #pragma unroll
-                for (int c = 0; c < M::NV; ++c) p.V[rec_index(m, c, k, M::NV, p.ntspan, p.n, p.nbig)] = s.v[c];
+                for (int c = 0; c < M::NV; ++c) p.V[rec_index(m, c, k, M::NV, p.ntspan, p.n, p.nmajor)] = s.v[c];
             }
         } else {
             const int lane = threadIdx.x & (WAVE - 1);
@@ -615,6 +745,42 @@ __device__ __forceinline__ void load_node(const KParams& p, int k, Node<M>& s, i
 // wide, the whole wavefront carries the node (ssa_wide); event tallies are
 // then kept by lane 0 only.  nrec holds the record at cur (loaded ahead so
 // that days without events wait for no memory access).
+// The node-local events of the day (time <= T), in key order (section 3.3:
+// exit, enter, internal transfer).  `counter`: the lane that counts them.
+template <class M>
+__device__ __forceinline__ void day_events(const KParams& p, Node<M>& s, int b, double T, uint32_t stream, int& cur,
+                                           int cend, int4& nrec, bool& dead, Tally& t, bool counter) {
+    while (cur < cend && (double)nrec.x <= T) {
+        const int rc = apply_event<M::NC>(nrec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
+        if (rc) {
+            raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
+            dead = true;
+            return;
+        }
+        t.ev += counter ? 1 : 0;
+        ++cur;
+        if (cur < cend) nrec = p.e1.rec[cur];
+    }
+}
+
+// A day of a node carried by a group of lanes: the SSA (called by every
+// lane of the wavefront) and then the day's node-local events.
+template <class M>
+__device__ __forceinline__ void group_day(const KParams& p, Node<M>& s, bool live, int b, int64_t day, uint32_t node,
+                                          uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec, bool& dead,
+                                          Tally& t, bool counter) {
+    const double T = (double)day;
+    const double t0 = b == 0 ? p.t0 : T - 1.0;
+    const int rc = ssa_group<M>(p, s, live, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr);
+    if (!live) return;
+    if (rc) {
+        raise_error(p.ctrl, b, PH_SSA, ord, rc);
+        dead = true;
+        return;
+    }
+    day_events<M>(p, s, b, T, stream, cur, cend, nrec, dead, t, counter);
+}
+
 template <class M, bool PIPE>
 __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, int64_t day, uint32_t node,
                                            uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec,
@@ -630,23 +796,13 @@ __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, 
         dead = true;
         return;
     }
-    while (cur < cend && (double)nrec.x <= T) {
-        rc = apply_event<M::NC>(nrec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
-        if (rc) {
-            raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
-            dead = true;
-            return;
-        }
-        t.ev += (!wide || (threadIdx.x & (WAVE - 1)) == 0) ? 1 : 0;
-        ++cur;
-        if (cur < cend) nrec = p.e1.rec[cur];
-    }
+    day_events<M>(p, s, b, T, stream, cur, cend, nrec, dead, t, !wide || (threadIdx.x & (WAVE - 1)) == 0);
 }
 
 // ---------------------------------------------------------------------------
 // free-running kernel (no external transfers)
 // ---------------------------------------------------------------------------
-template <class M, bool PIPE>
+template <class M, bool PIPE, bool GRP>
 __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
     KParams p = pa;
     p.seed = pa.rp->seed;
@@ -658,12 +814,17 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
         if (lane == 0) chunk = atomicAdd(&p.ctrl->work[p.group], 1u);
         chunk = __shfl(chunk, 0, WAVE);
         if (chunk >= (unsigned)p.nchunks) break;
-        // chunks [0, nbig): one heavy node per wavefront; then pack nodes per chunk
-        const bool wide = (int)chunk < p.nbig;
-        const int k = wide ? (int)chunk : p.nbig + ((int)chunk - p.nbig) * p.pack + lane;
-        const bool active = (wide || lane < p.pack) && k < p.n;
-        const bool owner = active && (!wide || lane == 0);  // writes records
-        Node<M> s;
+        // chunks [0, nbig): one heavy node per wavefront; then ngw chunks of
+        // WAVE / GRP_LANES nodes with GRP_LANES lanes each; then pack nodes per chunk
+        const int c = (int)chunk;
+        const bool wide = c < p.nbig;
+        const bool grp = GRP && !wide && c < p.nbig + p.ngw;
+        const int k = wide  ? c
+                      : grp ? p.nbig + (c - p.nbig) * (WAVE / GRP_LANES) + lane / GRP_LANES
+                            : p.nbig + p.ngrp + (c - p.nbig - p.ngw) * p.pack + lane;
+        const bool active = (wide || (grp ? k < p.nbig + p.ngrp : lane < p.pack)) && k < p.n;
+        const bool owner = active && (wide ? lane == 0 : grp ? lane % GRP_LANES == 0 : true);  // writes records
+        Node<M> s{};
         int run = 0, cur = 0, cend = 0;
         uint32_t node = 0, stream = 0;
         int64_t ord = 0;
@@ -678,8 +839,9 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
                     key_raw = __hip_atomic_load(&p.ctrl->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             const int64_t day = p.T1 + b;
+            if (grp) group_day<M>(p, s, active && !dead, b, day, node, stream, ord, cur, cend, nrec, dead, t, owner);
             if (active && !dead) {
-                ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
+                if (!grp) ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
                 if (!dead && !M::pts(s.v, s.u, s.ld, s.gd, day)) {
                     if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
                     dead = true;
@@ -752,7 +914,7 @@ __device__ __forceinline__ int xcd_block(int b, int b0, int nblk, int g) {
     return a + (r - rem) + (rem % XCDS) * g + rem / XCDS;
 }
 
-template <class M, bool PIPE>
+template <class M, bool PIPE, bool GRP>
 __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     KParams p = pa;
     p.seed = pa.rp->seed;
@@ -761,14 +923,19 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
     const int line_g = 32 / (p.pack * wpb);  // workgroups whose records fill one 128-byte line
-    const int gw = xcd_block(blockIdx.x, (p.nbig + wpb - 1) / wpb, gridDim.x, line_g) * wpb +
+    const int gw = xcd_block(blockIdx.x, (p.nbig + p.ngw + wpb - 1) / wpb, gridDim.x, line_g) * wpb +
                    (int)(threadIdx.x / WAVE);
-    // waves [0, nbig): one heavy node per wavefront; then pack nodes per wave
+    // waves [0, nbig): one heavy node per wavefront
     const bool wide = gw < p.nbig;
-    const int k = wide ? gw : p.nbig + (gw - p.nbig) * p.pack + lane;
-    const bool active = (wide || lane < p.pack) && k < p.n;
-    const bool owner = active && (!wide || lane == 0);
-    Node<M> s;
+    // then ngw waves of WAVE / GRP_LANES nodes with GRP_LANES lanes each
+    const bool grp = GRP && !wide && gw < p.nbig + p.ngw;
+    // then pack nodes per wave, one lane each
+    const int k = wide  ? gw
+                  : grp ? p.nbig + (gw - p.nbig) * (WAVE / GRP_LANES) + lane / GRP_LANES
+                        : p.nbig + p.ngrp + (gw - p.nbig - p.ngw) * p.pack + lane;
+    const bool active = (wide || (grp ? k < p.nbig + p.ngrp : lane < p.pack)) && k < p.n;
+    const bool owner = active && (wide ? lane == 0 : grp ? lane % GRP_LANES == 0 : true);
+    Node<M> s{};
     int run = 0, cur = 0, cend = 0, tcur = 0, tend = 0;
     uint32_t node = 0, stream = 0;
     int64_t ord = 0;
@@ -791,7 +958,10 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
                 key_raw = __hip_atomic_load(&p.ctrl->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const int64_t day = p.T1 + b;
-        if (active && !dead) ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
+        if (grp)
+            group_day<M>(p, s, active && !dead, b, day, node, stream, ord, cur, cend, nrec, dead, t, owner);
+        else if (active && !dead)
+            ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
 
         // this step's external transfers of the node, in key order.  The loop
         // is uniform over the wavefront and every lane that can move on does:
@@ -1032,15 +1202,15 @@ __global__ void init_kernel(KParams p, int nc, int nv, int first_rec, int reset_
         if (p.record == 0) {
             for (int m = 0; m < first_rec; ++m) {
                 for (int c = 0; c < nc; ++c)
-                    p.U[rec_index(m, c, k, nc, p.ntspan, p.n, p.nbig)] = p.u0[(size_t)c * p.n + k];
+                    p.U[rec_index(m, c, k, nc, p.ntspan, p.n, p.nmajor)] = p.u0[(size_t)c * p.n + k];
                 for (int c = 0; c < nv; ++c)
-                    p.V[rec_index(m, c, k, nv, p.ntspan, p.n, p.nbig)] = p.v0[(size_t)c * p.n + k];
+                    p.V[rec_index(m, c, k, nv, p.ntspan, p.n, p.nmajor)] = p.v0[(size_t)c * p.n + k];
             }
         }
     }
 }
 
-__global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv, int n, int ntspan, int nbig,
+__global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv, int n, int ntspan, int nmajor,
                               const int32_t* pos, int nn, int32_t* Uo, double* Vo) {
     const long long total = (long long)ntspan * nn;
     for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
@@ -1048,9 +1218,9 @@ __global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv,
         const int m = (int)(idx / nn), i = (int)(idx % nn);
         const int k = pos[i];
         if (Uo)
-            for (int c = 0; c < nc; ++c) Uo[((size_t)m * nn + i) * nc + c] = U[rec_index(m, c, k, nc, ntspan, n, nbig)];
+            for (int c = 0; c < nc; ++c) Uo[((size_t)m * nn + i) * nc + c] = U[rec_index(m, c, k, nc, ntspan, n, nmajor)];
         if (Vo)
-            for (int c = 0; c < nv; ++c) Vo[((size_t)m * nn + i) * nv + c] = V[rec_index(m, c, k, nv, ntspan, n, nbig)];
+            for (int c = 0; c < nv; ++c) Vo[((size_t)m * nn + i) * nv + c] = V[rec_index(m, c, k, nv, ntspan, n, nmajor)];
     }
 }
 
@@ -1091,24 +1261,26 @@ __global__ void prevalence_kernel(const unsigned long long* sums, int ntspan, in
 }
 
 template <class M, bool PIPE>
-const void* kernel_for(int mode) {
-    if (mode == MODE_FLOW) return (const void*)flow_kernel<M, PIPE>;
+const void* kernel_for(int mode, bool grp) {
+    // nodes on groups of lanes have their own instantiations, so that the
+    // other launches keep the register budget they need
+    if (mode == MODE_FLOW) return grp ? (const void*)flow_kernel<M, PIPE, true> : (const void*)flow_kernel<M, PIPE, false>;
     if (mode == MODE_BARRIER) return (const void*)sync_kernel<M, PIPE>;
-    return (const void*)free_kernel<M, PIPE>;
+    return grp ? (const void*)free_kernel<M, PIPE, true> : (const void*)free_kernel<M, PIPE, false>;
 }
 
 template <class M>
-const void* kernel_for(int mode, int pipeline) {
-    return pipeline ? kernel_for<M, true>(mode) : kernel_for<M, false>(mode);
+const void* kernel_for(int mode, int pipeline, bool grp) {
+    return pipeline ? kernel_for<M, true>(mode, grp) : kernel_for<M, false>(mode, grp);
 }
 
-const void* model_kernel(int model, int mode, int pipeline) {
+const void* model_kernel(int model, int mode, int pipeline, bool grp) {
     switch (model) {
-        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline);
-        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline);
-        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline);
-        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline);
-        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline);
+        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline, grp);
+        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline, grp);
+        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline, grp);
+        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline, grp);
+        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline, grp);
     }
     return nullptr;
 }
@@ -1125,7 +1297,7 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
 }
 
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st) {
-    const void* fn = model_kernel(model, p.mode, p.pipeline);
+    const void* fn = model_kernel(model, p.mode, p.pipeline, p.ngrp > 0);
     if (!fn) return hipErrorInvalidValue;
     KParams arg = p;
     void* args[] = {&arg};
@@ -1133,18 +1305,18 @@ hipError_t launch_group(int model, const KParams& p, int block, int blocks, size
     return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(block), args, (unsigned)shmem, st);
 }
 
-int max_blocks_per_cu(int model, int mode, int pipeline, int block, size_t shmem) {
-    const void* fn = model_kernel(model, mode, pipeline);
+int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem) {
+    const void* fn = model_kernel(model, mode, pipeline, grp);
     int n = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, shmem) != hipSuccess) return 0;
     return n;
 }
 
-hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nbig,
+hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nmajor,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st) {
     long long total = (long long)ntspan * nn;
     int blocks = (int)std::max<long long>(1, std::min<long long>((total + 255) / 256, 8192));
-    gather_kernel<<<blocks, 256, 0, st>>>(U, V, nc, nv, n, ntspan, nbig, pos, nn, Uo, Vo);
+    gather_kernel<<<blocks, 256, 0, st>>>(U, V, nc, nv, n, ntspan, nmajor, pos, nn, Uo, Vo);
     return hipGetLastError();
 }
 

@@ -123,7 +123,10 @@ def test_other_models(lib, kind):
                                   dict(lanes=64, wide=90, block=64, lattice=2), dict(pipeline=2, block=128),
                                   dict(pack=16), dict(pack=32, block=128), dict(pack=16, mode=2, lanes=1),
                                   dict(pack=16, lanes=64, wide=40, block=256), dict(pack=32, mode=1),
-                                  dict(pack=8, lanes=64, wide=90, block=64), dict(pack=4, block=128, pipeline=2)])
+                                  dict(pack=8, lanes=64, wide=90, block=64), dict(pack=4, block=128, pipeline=2),
+                                  dict(group=-1, lanes=1), dict(group=-1, lanes=64, wide=40, pack=8),
+                                  dict(group=200, mode=2, block=128), dict(group=-1, mode=1),
+                                  dict(group=77, pipeline=2, block=256, pack=16)])
 def test_launch_shape_does_not_change_bits(lib, opts):
     spec = W.config1(seed=11, Nn=600, days=50)
     ref = oracle_run(spec, 5, 0)
@@ -284,6 +287,40 @@ def test_wide_node_paths(lib, case, lattice):
     turnover, a negative compartment after a transition, a bad rate, and the
     2^24-step guard (in both paths), all against the oracle (state, counters,
     error key)."""
+    spec = _path_case(case)
+    Nn = np.asarray(spec.u0).shape[0]
+    m, ref, rc = _run_both(lib, spec, 23, 4, lanes=64, wide=Nn, lattice=lattice)
+    info = m.launch_info()
+    assert info["wide"] == Nn
+    _check_path_case(m, ref, rc, case)
+
+
+@pytest.mark.parametrize("case", ["extinction", "immigration", "sise", "sir_heavy", "neg_state", "bad_rate",
+                                  "step_limit", "step_limit_full_g"])
+def test_group_node_paths(lib, case):
+    """The same cases with every node on a group of 16 lanes (four nodes to
+    a wavefront, the lattice walk five steps per pass); the immigration
+    models, whose G does not mark both rates, fall back to one lane."""
+    spec = _path_case(case)
+    Nn = np.asarray(spec.u0).shape[0]
+    m, ref, rc = _run_both(lib, spec, 23, 4, lanes=1, group=-1)
+    info = m.launch_info()
+    assert info["group"] == (0 if case in ("immigration", "step_limit") else Nn), info
+    _check_path_case(m, ref, rc, case)
+
+
+def _check_path_case(m, ref, rc, case):
+    assert rc == ref["status"]
+    if rc:
+        e = m.error_info()
+        assert (e["code"], e["step"], e["phase"], e["index"]) == ref["error"]
+        return
+    _compare(m, ref, what=case)
+    c = m.counters()
+    assert (c["transitions"], c["node_days"]) == (ref["transitions"], ref["node_days"])
+
+
+def _path_case(case):
     rng = np.random.default_rng(17)
     tspan = np.arange(0, 6)
     if case == "extinction":
@@ -307,18 +344,7 @@ def test_wide_node_paths(lib, case, lattice):
         spec = W.sis_spec(np.array([[100000, 100000]]), np.arange(0, 2), 0.01, 0.5)
     else:
         spec = W.birth_death_spec(np.array([0, 0]), np.arange(0, 2), 3.0e7, 0.0, immigration=True)
-    Nn = np.asarray(spec.u0).shape[0]
-    m, ref, rc = _run_both(lib, spec, 23, 4, lanes=64, wide=Nn, lattice=lattice)
-    info = m.launch_info()
-    assert info["wide"] == Nn
-    assert rc == ref["status"]
-    if rc:
-        e = m.error_info()
-        assert (e["code"], e["step"], e["phase"], e["index"]) == ref["error"]
-        return
-    _compare(m, ref, what=case)
-    c = m.counters()
-    assert (c["transitions"], c["node_days"]) == (ref["transitions"], ref["node_days"])
+    return spec
 
 
 def _no_transfers(spec):
@@ -367,16 +393,18 @@ def test_free_running_cases(lib, case, pipeline):
             _compare(m, ref, run=r, what=f"batch run {r}")
 
 
-@pytest.mark.parametrize("pack", [4, 16, 32])
-def test_packed_wavefronts_batch(lib, pack):
-    """Fewer nodes per wavefront (the rest of its lanes idle): weekly sums of
-    a batch whose runs straddle wavefronts, and the launch reports it."""
+@pytest.mark.parametrize("pack,group", [(4, 0), (16, 0), (32, 0), (64, -1), (8, 150)])
+def test_packed_wavefronts_batch(lib, pack, group):
+    """Fewer nodes per wavefront (the rest of its lanes idle), or nodes on
+    groups of lanes: weekly sums of a batch whose runs straddle wavefronts,
+    and the launch reports it."""
     sets = W.ensemble_sets(seed=37, n_sets=4, replicates=2, days=60, nn_range=(20, 300))
     batch = [(st.spec, 2) for st in sets]
-    m = lib.Model(batch, record=lib.RECORD_SUMS, pack=pack)
+    m = lib.Model(batch, record=lib.RECORD_SUMS, pack=pack, group=group)
     info = m.launch_info()
-    _say("packed batch", pack, info)
+    _say("packed batch", pack, group, info)
     assert info["pack"] == pack
+    assert (info["group"] > 0) == (group != 0)
     m.run(29, 4)
     assert m.wait() == 0
     sums = m.sums()
