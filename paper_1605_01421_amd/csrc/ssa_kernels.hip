@@ -506,7 +506,7 @@ __device__ __forceinline__ int ssa_group(const KParams& p, Node<M>& s, bool live
         S0[c] = p.S[c];
         S1[c] = p.S[c + M::NC];
     }
-    unsigned long long nd = 0, ntr = 0;  // group-uniform
+    uint32_t nd = 0, ntr = 0;  // group-uniform
     int rc = 0;
     bool done = !live;
     uint32_t g = 0, mb = 0;
@@ -561,31 +561,24 @@ __device__ __forceinline__ int ssa_group(const KParams& p, Node<M>& s, bool live
         }
         // the steps in order: the state's checks, the step limit, the draw,
         // the day boundary, the transition
+        // (as selects: the groups of a wavefront stop at different steps)
         int kapp = 0, aapp = 0;  // transitions applied in this window, of the first kind
         bool stop = done;
 #pragma unroll
         for (int k = 0; k < GRP_W; ++k) {
-            if (!stop) {
-                if (ck[k]) {
-                    rc = (ck[k] & 1) ? E_NEG_STATE : (ck[k] & 2) ? E_BAD_RATE : 0;
-                    stop = true;
-                } else if (g + (uint32_t)k == STEP_LIMIT) {
-                    rc = E_BAD_RATE;
-                    stop = true;
-                } else {
-                    nd += 1;
-                    const double tn = t + tk[k];
-                    if (tn >= T) {
-                        stop = true;
-                    } else {
-                        t = tn;
-                        ntr += 1;
-                        kapp += 1;
-                        aapp += pd[k];
-                    }
-                }
-            }
+            const bool bad = !stop && ck[k] != 0;
+            const bool lim = !stop && !bad && g + (uint32_t)k == STEP_LIMIT;
+            const bool draw = !stop && !bad && !lim;
+            const double tn = t + tk[k];
+            const bool go = draw && !(tn >= T);
+            rc = bad ? ((ck[k] & 1) ? E_NEG_STATE : (ck[k] & 2) ? E_BAD_RATE : 0) : lim ? E_BAD_RATE : rc;
+            nd += draw ? 1u : 0u;
+            t = go ? tn : t;
+            kapp += go ? 1 : 0;
+            aapp += go ? pd[k] : 0;
+            stop = stop || !go;
         }
+        ntr += (uint32_t)kapp;
         if (!done) {
 #pragma unroll
             for (int c = 0; c < M::NC; ++c) s.u[c] += aapp * S0[c] + (kapp - aapp) * S1[c];
