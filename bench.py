@@ -65,9 +65,15 @@ def kernel_source_hash() -> str:
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel sources (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return measured_traffic_at(kernel, workload)[0]
+
+
+def measured_traffic_at(kernel: str, workload: str):
+    """(HBM bytes per launch, the launch shape the counters were taken at),
+    or (None, None) when there is no summary for the current sources."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
-        return None
+        return None, None
     vals = {}
     with open(path) as f:
         for line in f:
@@ -75,11 +81,11 @@ def measured_traffic(kernel: str, workload: str):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
-        return None
+        return None, None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]), vals.get("launch_shape")
     except (KeyError, ValueError):
-        return None
+        return None, None
 
 
 MODEL_NAMES = {0: "SIR", 1: "SIS", 2: "SISe", 3: "birth-death", 4: "immigration-death"}
@@ -327,6 +333,8 @@ def main():
     draws_per_launch = draws / args.steps
     achieved = draws_per_launch * OPS_PER_STEP / mean_kernel_s
     info = model.launch_info()
+    traffic_bytes, traffic_launch = measured_traffic_at(["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
+                                                        desc["workload"])
     out = {
         "metric": METRIC,
         "value": node_days / wall,
@@ -350,8 +358,9 @@ def main():
         "autotune_best_ms": tuned_ms,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": measured_traffic(["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
-                                                 desc["workload"]),
+                     "traffic": traffic_bytes,
+                     # the counters' launch shape: the autotuner may pick another one from run to run
+                     "traffic_launch": traffic_launch,
                      "kernel": ["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
                      "ssa_steps_per_launch": draws_per_launch, "ops_per_step": OPS_PER_STEP},
     }
