@@ -561,7 +561,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
         const uint32_t Tword = (uint32_t)(int32_t)Tint;
         uint64_t phase_err = NOERR;
 
-        /* ---- SSA to T, then this node's E1 events (Appendix A 7-21) ---- */
+        /* ---- SSA to T, then this node's E1 events (Appendix A) -------- */
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
         for (int i = 0; i < Nn; ++i) {
             int32_t *ui = u + (size_t)i * Nc;
@@ -663,7 +663,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
         if (phase_err != NOERR)
             goto fail;
 
-        /* ---- E2: external transfers, serially in key order (App. A 22) */
+        /* ---- E2: external transfers, serially in key order (Appendix A) */
         while (e2_cursor < n_e2) {
             int e = e2_list[e2_cursor];
             if ((double)m->ev_time[e] > T)
@@ -678,7 +678,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
             e2_cursor += 1;
         }
 
-        /* ---- post time step (App. A 23-25) ------------------------------ */
+        /* ---- post time step (Appendix A) ------------------------------- */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
         for (int i = 0; i < Nn; ++i) {
             double vnew[64];

@@ -124,7 +124,7 @@ __device__ __forceinline__ Transition<M> transition(const KParams& p, const Node
 }
 
 // Direct-method SSA of one node from time t to the day boundary T
-// (Appendix A, lines 8-19): lambda = w0 + w1, tau = -log(r1)/lambda, stop if
+// (Appendix A): lambda = w0 + w1, tau = -log(r1)/lambda, stop if
 // t + tau >= T, else pick the transition by inversion with r2, apply its
 // column of S and recompute the rates marked in G.  With PIPE the random
 // numbers of the next step (which do not depend on the state) are computed
