@@ -256,7 +256,7 @@ def main():
     ap.add_argument("--pipeline", type=int, default=0, help="0 auto, 1 on, 2 off")
     ap.add_argument("--pack", type=int, default=0, help="nodes per one-lane-per-node wavefront: 0 auto, 4, 8, 16, 32, 64")
     ap.add_argument("--group", type=int, default=0,
-                    help="nodes after the wide ones on a group of 16 lanes: 0 none/tuned, -1 all, N")
+                    help="nodes after the wide ones on a group of 8 lanes: 0 none/tuned, -1 all, N")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the run from a captured HIP graph: 1 on, 0 off, -1 on for batches without transfers")
     ap.add_argument("--no-cpu", action="store_true")

@@ -163,8 +163,8 @@ typedef struct {
                           grid-barrier kernel always packs 64; the results do
                           not depend on it. */
     int32_t group;     /* how many nodes after the wavefront-wide ones get a
-                          group of 16 lanes each (4 nodes a wavefront), on
-                          which the lattice walk covers 5 steps per pass: 0
+                          group of 8 lanes each (8 nodes a wavefront), on
+                          which the lattice walk covers 3 steps per pass: 0
                           none (the autotuner may choose some), -1 all, else
                           that many.  Only where the lattice walk applies (see
                           lattice) and not in the grid-barrier kernel; the

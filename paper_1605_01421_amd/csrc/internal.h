@@ -9,7 +9,7 @@ namespace siminf {
 constexpr int MAX_NC = 4;     // largest compartment count of the built-in models
 constexpr int MAX_NT = 2;     // every built-in model has two transitions
 constexpr int WAVE = 64;      // gfx950 wavefront
-constexpr int GROUP_LANES = 16;  // lanes of a node carried by a group (4 groups a wavefront)
+constexpr int GROUP_LANES = 8;  // lanes of a node carried by a group (8 groups a wavefront)
 constexpr int MAX_GROUPS = 8; // one group per built-in model present in a batch
 
 // phases of one unit of time, in the order of Appendix A

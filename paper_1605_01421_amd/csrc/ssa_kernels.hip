@@ -473,18 +473,20 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
 // The lattice walk for a node carried by GRP_LANES lanes (a group; a
 // wavefront holds WAVE / GRP_LANES of them, each on its own node).  Lane
 // (lk, la) of a group evaluates the state lk steps ahead with la transitions
-// of the first kind, for the next GRP_W steps (GRP_POINTS lanes; the last
-// lane of the group idles in the pass).  The group's lanes draw GRP_BLOCK
-// steps' random numbers at once (lane j draws step base + j).  The path is
+// of the first kind, for the next GRP_W steps (GRP_POINTS lanes; the other
+// lanes of the group idle in the pass).  The group's lanes draw GRP_BLOCK
+// steps' random numbers at once (lane j draws step base + j).  Eight lanes
+// and three steps a pass measured faster than sixteen and five, or four and
+// two, on SIR with events over 10,000 nodes.  The path is
 // read from the group's bits of one ballot; tau and the check of each point
 // on it are then gathered and the steps are walked in order, each lane of
 // the group doing the same (group-uniform) work, with exactly the checks and
 // counts of ssa_to_boundary.  Must be called by every lane of the wavefront
 // (it shuffles and ballots); `live` marks the groups whose node steps.
 constexpr int GRP_LANES = GROUP_LANES;
-constexpr int GRP_W = 5;
+constexpr int GRP_W = 3;
 constexpr int GRP_POINTS = GRP_W * (GRP_W + 1) / 2;
-constexpr int GRP_BLOCK = 15;
+constexpr int GRP_BLOCK = 6;
 static_assert(GRP_POINTS < GRP_LANES && GRP_BLOCK <= GRP_LANES && GRP_BLOCK % GRP_W == 0 && WAVE % GRP_LANES == 0,
               "a group's lattice must fit its lanes");
 

@@ -298,8 +298,8 @@ def test_wide_node_paths(lib, case, lattice):
 @pytest.mark.parametrize("case", ["extinction", "immigration", "sise", "sir_heavy", "neg_state", "bad_rate",
                                   "step_limit", "step_limit_full_g"])
 def test_group_node_paths(lib, case):
-    """The same cases with every node on a group of 16 lanes (four nodes to
-    a wavefront, the lattice walk five steps per pass); the immigration
+    """The same cases with every node on a group of 8 lanes (eight nodes to
+    a wavefront, the lattice walk three steps per pass); the immigration
     models, whose G does not mark both rates, fall back to one lane."""
     spec = _path_case(case)
     Nn = np.asarray(spec.u0).shape[0]
