@@ -68,6 +68,27 @@ def test_graph_full_records_and_reconfigure(lib):
     assert np.array_equal(U, oracle.run(spec, 9, 2, nthreads=NTHREADS)["U"])
 
 
+def test_graph_replays_with_groups(lib):
+    """Graph replay of a launch with nodes on groups of lanes and 8 nodes to
+    a one-lane wavefront, against plain launches and the oracle."""
+    import oracle
+    spec = W.config0()
+    # lanes=1: no wavefront-wide nodes (the 100 equal nodes would all pass
+    # the wide cut), so 40 nodes take groups and 60 one lane each
+    g = lib.Model(spec, graph=1, group=40, pack=8, lanes=1)
+    plain = lib.Model(spec, group=40, pack=8, lanes=1)
+    assert g.launch_info()["group"] == 40
+    for seed in (4, 19, 4):
+        _say("graph with groups seed", seed)
+        g.run(seed, 1)
+        assert g.wait() == 0
+        plain.run(seed, 1)
+        assert plain.wait() == 0
+        U, _ = g.trajectory()
+        assert np.array_equal(U, plain.trajectory()[0])
+    assert np.array_equal(U, oracle.run(spec, 4, 1, nthreads=NTHREADS)["U"])
+
+
 def test_graph_refused_with_transfers(lib):
     spec = W.config1(seed=3, Nn=200, days=20)
     m = lib.Model(spec, graph=1)

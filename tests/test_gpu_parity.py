@@ -143,6 +143,27 @@ def test_launch_shape_does_not_change_bits(lib, opts):
     _compare(m0, ref0, what="free " + str(opts))
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_with_transfers_on_groups(lib, mode):
+    """Runs with external transfers batched in one launch, every node on a
+    group of lanes (dataflow kernel) or the barrier kernel, against the
+    oracle run by run."""
+    specs = [W.config1(seed=s, Nn=nn, days=45) for s, nn in ((5, 300), (9, 170))]
+    batch = [(specs[0], 2), (specs[1], 1)]
+    m = lib.Model(batch, group=-1, pack=8, mode=mode)
+    info = m.launch_info()
+    _say("batch with transfers", mode, info)
+    assert (info["group"] > 0) == (mode == 2)
+    m.run(13, 7)
+    assert m.wait() == 0
+    r = 0
+    for spec, reps in batch:
+        for _ in range(reps):
+            ref = oracle_run(spec, 13, 7 + r)
+            _compare(m, ref, run=r, what=f"batch run {r}")
+            r += 1
+
+
 def test_batch_equals_individual_runs(lib):
     a = W.sir_spec(np.tile([200, 3, 0], (70, 1)), np.arange(0, 41), 0.3, 0.1)
     b = W.sise_spec(np.tile([90, 6], (45, 1)), np.arange(0, 41), 0.02, 0.1, 1.0, (0.1, 0.12, 0.1, 0.11))
@@ -190,8 +211,9 @@ def test_prevalence_quantiles(lib):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("group", [0, -1])
 @pytest.mark.parametrize("case", ["overdraw_e1", "overdraw_e2", "negative_rate"])
-def test_first_error_matches_oracle(lib, case, mode):
+def test_first_error_matches_oracle(lib, case, mode, group):
     u0 = np.array([[5, 0, 0], [5, 0, 0], [5, 0, 0]])
     beta = 0.0
     if case == "overdraw_e1":
@@ -205,7 +227,7 @@ def test_first_error_matches_oracle(lib, case, mode):
         beta = -0.1
         rows = []
     spec = W.sir_spec(u0, [0, 1, 2, 3, 4], beta, 0.1, events=W.make_events(rows))
-    m, ref, rc = _run_both(lib, spec, 1, 0, mode=mode)
+    m, ref, rc = _run_both(lib, spec, 1, 0, mode=mode, group=group, lanes=1 if group else 0)
     info = m.error_info()
     assert rc == ref["status"] != 0
     assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
