@@ -220,8 +220,8 @@ int default_group(const Group& g, int nbig, int div) {
 }
 
 // Kernel and launch shape of one group.  want_mode applies to groups with
-// external transfers: 0 auto (dataflow if every node wavefront and the worker
-// fit on the device at once, else grid barrier), 1 barrier, 2 dataflow.
+// external transfers: 0 auto (dataflow if every node wavefront fits on the
+// device at once, else grid barrier), 1 barrier, 2 dataflow.
 int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode, int pack, int ngrp) {
     drop_graph(m);
     KParams& p = g.p;
