@@ -736,12 +736,10 @@ __device__ __forceinline__ void load_node(const KParams& p, int k, Node<M>& s, i
     if (cur < cend) nrec = p.e1.rec[cur];
 }
 
-// SSA to day boundary b, then the node's E1 events with time <= T.  With
-// wide, the whole wavefront carries the node (ssa_wide); event tallies are
-// then kept by lane 0 only.  nrec holds the record at cur (loaded ahead so
-// that days without events wait for no memory access).
 // The node-local events of the day (time <= T), in key order (section 3.3:
 // exit, enter, internal transfer).  `counter`: the lane that counts them.
+// nrec holds the record at cur, loaded ahead so that days without events
+// wait for no memory access.
 template <class M>
 __device__ __forceinline__ void day_events(const KParams& p, Node<M>& s, int b, double T, uint32_t stream, int& cur,
                                            int cend, int4& nrec, bool& dead, Tally& t, bool counter) {
@@ -776,6 +774,10 @@ __device__ __forceinline__ void group_day(const KParams& p, Node<M>& s, bool liv
     day_events<M>(p, s, b, T, stream, cur, cend, nrec, dead, t, counter);
 }
 
+// SSA to day boundary b, then the node's E1 events with time <= T.  With
+// wide, the whole wavefront carries the node (the lattice walk, or the plain
+// chain when G does not mark both rates); event tallies are then kept by
+// lane 0 only.
 template <class M, bool PIPE>
 __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, int64_t day, uint32_t node,
                                            uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec,
