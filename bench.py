@@ -120,11 +120,11 @@ def build_workload(name):
     a batch ([(spec, replicates)])."""
     from paper_1605_01421_amd import workloads as W
     if name == "sir-events":
-        spec = W.config1()
+        spec = W.sir_with_events()
     elif name == "sir-plain":
-        spec = W.config0()
+        spec = W.plain_sir()
     elif name == "sise-events":
-        spec = W.config2()
+        spec = W.sise_with_events()
     elif name == "ensemble":
         sets = W.ensemble_sets(seed=3, n_sets=64, replicates=64)
         nodes = sum(s.spec.Nn for s in sets) * 64

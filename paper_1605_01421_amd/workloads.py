@@ -197,7 +197,7 @@ def sir_event_example(infect=True):
 
 # ---- benchmark workloads --------------------------------------------------
 
-def config0() -> ModelSpec:
+def plain_sir() -> ModelSpec:
     """Plain SIR: 100 nodes of (990, 10, 0), beta 0.16, gamma 0.077, tspan 1..100."""
     u0 = np.tile(np.array([990, 10, 0], dtype=np.int32), (100, 1))
     return sir_spec(u0, np.arange(1, 101), 0.16, 0.077, name="sir-100-plain")
@@ -262,7 +262,7 @@ def _demographic_events(rng, Nn, tot, days, birth, exit_, ship_frac, select_all,
     return {k: np.concatenate(v) if v else np.zeros(0) for k, v in out.items()}
 
 
-def config1(seed: int = 1, Nn: int = 10_000, days: int = 365) -> ModelSpec:
+def sir_with_events(seed: int = 1, Nn: int = 10_000, days: int = 365) -> ModelSpec:
     """SIR with scheduled events: lognormal node sizes (median 100, sigma 1,
     clipped to 1..5000), 1% infected, daily births Poisson(0.0005 N) into S,
     exits Binomial(N, 0.0003) over S/I/R, 0.5% of the nodes ship a
@@ -277,7 +277,7 @@ def config1(seed: int = 1, Nn: int = 10_000, days: int = 365) -> ModelSpec:
                     name=f"sir-events-{Nn}x{days}")
 
 
-def config2(seed: int = 2, Nn: int = 37_000, days: int = 3650) -> ModelSpec:
+def sise_with_events(seed: int = 2, Nn: int = 37_000, days: int = 3650) -> ModelSpec:
     """SISe with events: lognormal sizes (median 40, sigma 0.39, about 1.6M
     individuals for 37,000 nodes), 10% of nodes start with floor(5% of S)
     infected, phi0 = 0, upsilon 0.0175, gamma 0.1, alpha 1, quarterly decay

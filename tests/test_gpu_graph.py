@@ -51,7 +51,7 @@ def test_graph_replays_equal_plain_runs(lib):
 
 def test_graph_full_records_and_reconfigure(lib):
     import oracle
-    spec = W.config0()
+    spec = W.plain_sir()
     m = lib.Model(spec, graph=1)
     for seed in (123, 7):
         _say("graph full records seed", seed)
@@ -72,7 +72,7 @@ def test_graph_replays_with_groups(lib):
     """Graph replay of a launch with nodes on groups of lanes and 8 nodes to
     a one-lane wavefront, against plain launches and the oracle."""
     import oracle
-    spec = W.config0()
+    spec = W.plain_sir()
     # lanes=1: no wavefront-wide nodes (the 100 equal nodes would all pass
     # the wide cut), so 40 nodes take groups and 60 one lane each
     g = lib.Model(spec, graph=1, group=40, pack=8, lanes=1)
@@ -90,7 +90,7 @@ def test_graph_replays_with_groups(lib):
 
 
 def test_graph_refused_with_transfers(lib):
-    spec = W.config1(seed=3, Nn=200, days=20)
+    spec = W.sir_with_events(seed=3, Nn=200, days=20)
     m = lib.Model(spec, graph=1)
     with pytest.raises(lib.SiminfError) as e:
         m.run(1, 0)

@@ -54,7 +54,7 @@ def oracle_run(spec, seed, stream):
 
 
 def test_plain_sir_100_nodes(lib):
-    spec = W.config0()
+    spec = W.plain_sir()
     m, ref, rc = _run_both(lib, spec, 123)
     assert rc == 0 and ref["status"] == 0
     _compare(m, ref, what="sir-100")
@@ -77,7 +77,7 @@ def test_paper_five_node_event_example(lib, infect):
 
 @pytest.mark.parametrize("Nn,days,seed", [(257, 40, 1), (1000, 90, 7)])
 def test_sir_with_events_small(lib, Nn, days, seed):
-    spec = W.config1(seed=seed, Nn=Nn, days=days)
+    spec = W.sir_with_events(seed=seed, Nn=Nn, days=days)
     m, ref, rc = _run_both(lib, spec, 42 + seed, 5)
     assert rc == 0 and ref["status"] == 0
     _compare(m, ref, what=spec.name)
@@ -87,7 +87,7 @@ def test_sir_with_events_small(lib, Nn, days, seed):
 
 @pytest.mark.parametrize("mode", [1, 2])
 def test_sise_with_events_small(lib, mode):
-    spec = W.config2(seed=4, Nn=700, days=200)
+    spec = W.sise_with_events(seed=4, Nn=700, days=200)
     m, ref, rc = _run_both(lib, spec, 9, 2, mode=mode)
     assert rc == 0 and ref["status"] == 0
     _compare(m, ref, what=spec.name)
@@ -128,14 +128,14 @@ def test_other_models(lib, kind):
                                   dict(group=200, mode=2, block=128), dict(group=-1, mode=1),
                                   dict(group=77, pipeline=2, block=256, pack=16)])
 def test_launch_shape_does_not_change_bits(lib, opts):
-    spec = W.config1(seed=11, Nn=600, days=50)
+    spec = W.sir_with_events(seed=11, Nn=600, days=50)
     ref = oracle_run(spec, 5, 0)
     m = lib.Model(spec, **opts)
     _say("launch", opts, m.launch_info())
     m.run(5, 0)
     assert m.wait() == 0
     _compare(m, ref, what=str(opts))
-    free = W.config0()
+    free = W.plain_sir()
     ref0 = oracle_run(free, 8, 3)
     m0 = lib.Model(free, **opts)
     m0.run(8, 3)
@@ -148,7 +148,7 @@ def test_batch_with_transfers_on_groups(lib, mode):
     """Runs with external transfers batched in one launch, every node on a
     group of lanes (dataflow kernel) or the barrier kernel, against the
     oracle run by run."""
-    specs = [W.config1(seed=s, Nn=nn, days=45) for s, nn in ((5, 300), (9, 170))]
+    specs = [W.sir_with_events(seed=s, Nn=nn, days=45) for s, nn in ((5, 300), (9, 170))]
     batch = [(specs[0], 2), (specs[1], 1)]
     m = lib.Model(batch, group=-1, pack=8, mode=mode)
     info = m.launch_info()
@@ -235,7 +235,7 @@ def test_first_error_matches_oracle(lib, case, mode, group):
 
 @pytest.mark.parametrize("opts", [dict(pack=2), dict(pack=48), dict(block=96), dict(lanes=2), dict(lattice=3)])
 def test_invalid_options_rejected(lib, opts):
-    spec = W.config0()
+    spec = W.plain_sir()
     with pytest.raises(lib.SiminfError) as e:
         lib.Model(spec, **opts)
     assert e.value.code in (-1, -2)
@@ -260,17 +260,17 @@ def test_trajectory_to_device(lib):
 @pytest.mark.parametrize("mode", [1, 2])
 def test_sir_events_full_size(lib, mode):
     """10,000 nodes, 365 days, the benchmark workload: whole trajectory."""
-    spec = W.config1()
-    _say("config1 full", spec.Nn, len(spec.events["time"]))
+    spec = W.sir_with_events()
+    _say("SIR with events, full size", spec.Nn, len(spec.events["time"]))
     m, ref, rc = _run_both(lib, spec, 2024, 0, mode=mode)
     assert rc == 0 and ref["status"] == 0
-    _compare(m, ref, what="config1 full")
+    _compare(m, ref, what="SIR with events, full size")
     c = m.counters()
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
 
 
 def test_autotune_keeps_bits(lib):
-    spec = W.config1(seed=13, Nn=800, days=45)
+    spec = W.sir_with_events(seed=13, Nn=800, days=45)
     ref = oracle_run(spec, 77, 2)
     m = lib.Model(spec)
     _say("autotune")
@@ -381,7 +381,7 @@ def test_free_running_cases(lib, case, pipeline):
     computed ahead (pipeline 1) or not (2): node-local events, full records,
     weekly sums over uneven runs and a failing node, against the oracle."""
     if case == "events":
-        spec = _no_transfers(W.config1(seed=21, Nn=900, days=80))
+        spec = _no_transfers(W.sir_with_events(seed=21, Nn=900, days=80))
         m, ref, rc = _run_both(lib, spec, 41, 3, pipeline=pipeline)
         assert rc == 0 and ref["status"] == 0
         _compare(m, ref, what=case)

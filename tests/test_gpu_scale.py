@@ -38,8 +38,8 @@ def lib():
 
 def test_sise_events_full_size(lib):
     import oracle
-    spec = W.config2()
-    _say("config2 full", spec.Nn, len(spec.events["time"]), "threads", NTHREADS)
+    spec = W.sise_with_events()
+    _say("SISe with events, full size", spec.Nn, len(spec.events["time"]), "threads", NTHREADS)
     m = lib.Model(spec)
     m.run(31, 5)
     rc = m.wait()

@@ -153,7 +153,7 @@ def test_event_totals_follow_deterministic_recursion(orc):
     exactly (SIR transitions conserve the total).  The expected totals are
     replayed here in the paper's same-day order: all nodes' exits and enters
     (E1) before the external transfers (E2) in table order."""
-    spec = W.config1(seed=3, Nn=300, days=80)
+    spec = W.sir_with_events(seed=3, Nn=300, days=80)
     r = orc.run(spec, seed=17, stream=4)
     assert r["status"] == 0
     ev = spec.events

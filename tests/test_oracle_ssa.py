@@ -157,7 +157,7 @@ def test_sir_large_population_follows_ode(orc):
 
 def test_conservation_without_events(orc):
     """P5a: S+I+R (SIR) and S+I (SISe) are constant per node without events."""
-    spec = W.config0()
+    spec = W.plain_sir()
     r = orc.run(spec, seed=123, stream=0)
     tot = r["U"].sum(axis=2)
     assert (tot == 1000).all()
@@ -228,7 +228,7 @@ def test_hypergeometric_event_sampling(orc):
 
 def test_thread_count_does_not_change_bits(orc):
     """The counter RNG makes the trajectory independent of the schedule."""
-    spec = W.config1(seed=5, Nn=400, days=60)
+    spec = W.sir_with_events(seed=5, Nn=400, days=60)
     a = orc.run(spec, seed=42, stream=7, nthreads=1)
     b = orc.run(spec, seed=42, stream=7, nthreads=8)
     assert a["status"] == 0 and a["events"] > 100
