@@ -53,3 +53,16 @@ def test_product_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "siminf_oracle" not in text, f
+
+
+@pytest.mark.parametrize("opts,code", [(dict(pack=3), -1), (dict(pack=128), -1), (dict(group=-2), -1),
+                                       (dict(block=96), -1), (dict(block=512), -1), (dict(lattice=3), -1),
+                                       (dict(pipeline=3), -1), (dict(mode=3), -1), (dict(graph=2), -1),
+                                       (dict(wait_ms=-1), -1), (dict(record=5), -1), (dict(lanes=2), -2)])
+def test_invalid_options_rejected_before_the_device(opts, code):
+    """siminf_create checks the launch options before it touches a device,
+    so a bad value is reported the same way with or without a GPU."""
+    from paper_1605_01421_amd import siminf, workloads as W
+    with pytest.raises(siminf.SiminfError) as e:
+        siminf.Model(W.plain_sir(), **opts)
+    assert e.value.code == code
