@@ -249,7 +249,8 @@ int siminf_launch_info(const siminf_model *m, int32_t out[8]);
  * wide-node choices again with it; then (with group = 0) groups of lanes for
  * the heaviest eighth, quarter or half of the nodes after the wide ones, or
  * for all of them, each with the packing chosen so far and with 16 and 8
- * nodes per one-lane wavefront.  Every shape gives bit-identical results;
+ * nodes per one-lane wavefront, and finally the other pipelining setting on
+ * the best shape.  Every shape gives bit-identical results;
  * the handle's recorded results are overwritten.  With the environment
  * variable SIMINF_AUTOTUNE_LOG set (and not "0"), each candidate's time is
  * printed to stderr as it is measured. */

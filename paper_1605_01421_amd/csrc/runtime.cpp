@@ -1134,6 +1134,11 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
             for (int pack : packs)
                 for (int gdiv : {8, 4, 2, 1}) consider({third.block, third.wide_div, third.pipeline, pack, gdiv});
         }
+        // pipelining was chosen on the first sweep's shape: try the other
+        // setting on the final one
+        Cand last = pick;
+        last.pipeline = pick.pipeline == 1 ? 2 : 1;
+        consider(last);
     }
     for (Group& g : m->groups) {
         const int nb = default_wide(m, g, pick.wide_div);
