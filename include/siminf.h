@@ -56,10 +56,14 @@ enum {
     SIMINF_E_ALLOC = -3,          /* device or host allocation failed */
     SIMINF_E_DEVICE = -4,         /* HIP runtime error, or an in-kernel barrier timed out */
     SIMINF_E_NEG_STATE = -5,      /* a transition made a compartment negative (App. A, 17) */
-    SIMINF_E_BAD_RATE = -6,       /* a transition rate was negative or not finite */
+    SIMINF_E_BAD_RATE = -6,       /* a transition rate was negative or not finite (App. A: the
+                                     rates must be valid propensities) */
     SIMINF_E_EVENT_OVERDRAW = -7, /* an event asked for more individuals than exist (sec. 4.1.2) */
     SIMINF_E_EVENT_INDEX = -8,    /* an event names a node / select / shift out of range */
-    SIMINF_E_PTS = -9             /* the post-time-step function failed (non-finite state) */
+    SIMINF_E_PTS = -9,            /* the post-time-step function failed (non-finite state) */
+    SIMINF_E_STEP_LIMIT = -10     /* implementation limit, not the method's: a node needed more
+                                     than 2^24 SSA draws within one unit of time (the draw index
+                                     is the first Philox counter word; see siminf_run) */
 };
 
 /* ---- built-in models (the TRFun / PTSFun pairs of section 3.4.1) ----------
@@ -192,43 +196,78 @@ int siminf_create(const siminf_spec *spec, const siminf_options *opt, siminf_mod
 int siminf_create_batch(const siminf_spec *specs, int32_t nspecs, const int32_t *replicates,
                         const siminf_options *opt, siminf_model **out);
 
-/* Enqueues one complete run (all days, events, post-time steps and
- * records) on hip_stream (a hipStream_t; NULL = the null stream) and
- * returns without waiting.  Runs of the same handle must not overlap.
- * seed is the Philox key; stream_base < 2^24 - (number of runs). */
+/* Enqueues one complete run on hip_stream (a hipStream_t; NULL = the null
+ * stream) and returns without waiting: the whole of run() in section 3.4.2
+ * and the Appendix A algorithm -- for every unit of time from
+ * floor(tspan[0]) + 1 to ceil(tspan[Ntspan-1]), the direct-method SSA of
+ * every node up to the boundary, the node's exit / enter / internal-transfer
+ * events, the external transfers in table order, the post-time-step
+ * function, and the U/V records of the tspan points passed (section 3.3,
+ * eq. numstep3, Table 1).  seed is the Philox key (the paper's GSL seed);
+ * run r of the handle uses stream stream_base + r, and stream_base + runs
+ * must not exceed 2^24.  Draws are keyed by the absolute day (the counter
+ * word (uint32)T), so a simulation split into consecutive runs that each
+ * start from the previous one's last state equals one run over the whole
+ * span: this replaces a day-offset argument.  Runs of the same handle must
+ * not overlap; a new run first waits for the previous one.  Errors in the
+ * run are reported by siminf_wait; this call returns SIMINF_E_ARG for a bad
+ * stream range, SIMINF_E_UNSUPPORTED when options.graph is set for a model
+ * with external transfers, SIMINF_E_DEVICE when a launch fails.  Each node-
+ * day may take at most 2^24 SSA draws (SIMINF_E_STEP_LIMIT). */
 int siminf_run(siminf_model *m, uint64_t seed, uint32_t stream_base, void *hip_stream);
 
 /* Waits for the last run and returns its status: 0 or the code of the first
- * error in the serial order (day, phase SSA < E1 < E2 < PTS, node or event
- * index), as siminf_error_info reports. */
+ * error in the serial order of Appendix A (day step, then phase SSA < E1 < E2
+ * < PTS, then node or event index), which siminf_error_info describes; a
+ * failing run stops after that day.  SIMINF_E_DEVICE if a kernel failed or a
+ * wait inside it passed options.wait_ms. */
 int siminf_wait(siminf_model *m);
 
-/* Copies run `run`'s recorded U (Nc*Nn x Ntspan, column-major: node i's
- * compartment c at tspan[k] is U[c + i*Nc + k*Nc*Nn]) and V (Nv*Nn x
- * Ntspan, same layout) to U / V (either may be NULL).  dst_is_device != 0
- * means U and V are device pointers on the model's device.  Waits for the
- * last run.  Requires SIMINF_RECORD_FULL. */
+/* The trajectory of section 3.4.2 (trajectory(), Table 1): copies run
+ * `run`'s recorded U (Nc*Nn x Ntspan, column-major: node i's compartment c at
+ * tspan[k] is U[c + i*Nc + k*Nc*Nn]) and V (Nv*Nn x Ntspan, same layout) to
+ * U / V (either may be NULL).  dst_is_device != 0 means U and V are device
+ * pointers on the model's device; otherwise host memory owned by the caller
+ * (staged through a device buffer the handle keeps for later calls).  Waits
+ * for the last run (synchronising only its stream).  Requires
+ * SIMINF_RECORD_FULL, else SIMINF_E_ARG.  Returns the run's status: after a
+ * failed run the records are copied too, but those after the failing day are
+ * undefined. */
 int siminf_trajectory(siminf_model *m, int32_t run, int32_t *U, double *V, int32_t dst_is_device);
 
-/* Copies the per-run compartment sums, int64 [runs][Ntspan][Nc] row-major,
- * to sums (host, or device if dst_is_device).  Requires SIMINF_RECORD_SUMS. */
+/* Copies the per-run compartment sums over all nodes at each tspan point
+ * (the numerators and denominators of prevalence() in section 4.2), int64
+ * [runs][Ntspan][Nc] row-major, to sums (host, or device if dst_is_device).
+ * Requires SIMINF_RECORD_SUMS, else SIMINF_E_ARG.  Returns the run's status
+ * like siminf_trajectory. */
 int siminf_sums(siminf_model *m, int64_t *sums, int32_t dst_is_device);
 
-/* Counters of the last run: out[0] transitions executed, out[1] node-days
- * simulated, out[2] scheduled events applied, out[3] SSA steps (Philox
- * blocks drawn: the transitions plus each node-day's final step that ends
- * at the day boundary).  Waits for the last run. */
+/* Counters of the last run (Appendix A): out[0] transitions executed
+ * (line 17 of each step that stays inside the day), out[1] node-days
+ * simulated, out[2] scheduled events applied (section 3.3), out[3] SSA
+ * draws (Philox blocks: the transitions plus each node-day's final draw
+ * whose step crosses the boundary).  Waits for the last run; after a failed
+ * run they count the work done up to the failure in each node. */
 int siminf_counters(siminf_model *m, uint64_t out[4]);
 
 /* Sizes of a handle: out[0] runs, out[1] total nodes, out[2] Ntspan,
  * out[3] Nc (largest over specs), out[4] Nv (largest), out[5] day steps. */
 int siminf_shape(const siminf_model *m, int64_t out[6]);
 
-/* First error of the last run (or of create): code, 0-based day step,
- * phase (0 SSA, 1 E1, 2 E2, 3 PTS; -1 = create), index (node within its
- * run for SSA/PTS, event input index for events) and run. */
+/* First error of the last run (or of create), in the serial order of
+ * Appendix A and the error rules of sections 3.3 and 3.4: code, 0-based day
+ * step, phase (0 SSA, 1 E1, 2 E2, 3 PTS; -1 = create), index (node within
+ * its run for SSA/PTS, event input index for events and for a static event
+ * error found by create) and run.  Any pointer may be NULL. */
 int siminf_error_info(const siminf_model *m, int32_t *code, int64_t *step, int32_t *phase,
                       int64_t *index, int32_t *run);
+
+/* The same error as a NUL-terminated message of at most cap bytes (cap > 0)
+ * in buf, owned by the caller, e.g. "SIMINF_E_EVENT_OVERDRAW at day step 37
+ * in an external transfer, event 1234 of run 0: an event asked for more
+ * individuals than the selected compartments hold"; "SIMINF_OK" when there
+ * was none.  A longer message is truncated. */
+int siminf_error_message(const siminf_model *m, char *buf, size_t cap);
 
 /* Launch configuration chosen for the handle (its first model group):
  * out[0] threads per block, out[1] blocks, out[2] kernel (0 free-running,
@@ -262,7 +301,9 @@ int siminf_autotune(siminf_model *m, uint64_t seed, int32_t repeats, void *hip_s
  * per-run initialisation.  Waits for the last run. */
 int siminf_timing(siminf_model *m, double out[2]);
 
-/* Frees the handle and its device memory (waits for its last run). */
+/* Frees the handle and its device memory (waits for its last run).  Call it
+ * while the HIP runtime is alive (before the process starts to exit); a
+ * handle left open at exit is reclaimed with the process. */
 void siminf_destroy(siminf_model *m);
 
 /* Status code name, e.g. "SIMINF_E_EVENT_OVERDRAW". */

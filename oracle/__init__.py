@@ -30,7 +30,7 @@ _LIB = os.path.join(_HERE, "libsiminf_oracle.so")
 MODELS = {"SIR": 0, "SIS": 1, "SISE": 2, "BIRTH_DEATH": 3, "IMMIGRATION_DEATH": 4}
 ERRORS = {0: "ok", -1: "E_ARG", -2: "E_UNSUPPORTED", -3: "E_ALLOC",
           -5: "E_NEG_STATE", -6: "E_BAD_RATE", -7: "E_EVENT_OVERDRAW",
-          -8: "E_EVENT_INDEX", -9: "E_PTS"}
+          -8: "E_EVENT_INDEX", -9: "E_PTS", -10: "E_STEP_LIMIT"}
 
 
 def build(verbose: bool = False) -> str:

@@ -51,14 +51,22 @@
 #define OR_E_EVENT_OVERDRAW (-7)
 #define OR_E_EVENT_INDEX (-8)
 #define OR_E_PTS (-9)
+#define OR_E_STEP_LIMIT (-10)
+
+/* Implementation limit, not part of the method: the Appendix A loop has no
+ * bound on the number of steps a node takes within one unit of time.  Here
+ * the draw index k of a node-day is the first Philox counter word, so a
+ * node-day owns 2^32 distinct blocks and cannot go past that without
+ * repeating draws; the limit is set far below, at 2^24 draws, so that one
+ * node with exploding rates ends the run instead of holding it for hours.
+ * A node that would need the draw with index OR_STEP_LIMIT (counted from 0)
+ * stops the run with OR_E_STEP_LIMIT, keyed like any SSA error (day step,
+ * phase SSA, node); the test sits after the lambda test and before the
+ * draw, so every node-day that needs at most OR_STEP_LIMIT draws is the
+ * method's own result. */
+#define OR_STEP_LIMIT (1u << 24)
 
 /* phases of one unit of time, in the order of Appendix A */
-/* Reading of the method for runaway rates: a node that would need a draw
- * with index OR_STEP_LIMIT (counted from 0) within one day step is stopped
- * with E_BAD_RATE, checked after the lambda test and before the draw.  The
- * paper's algorithm has no such guard; it bounds the loop when the rates are
- * so large that tau no longer advances t at binary64 resolution. */
-#define OR_STEP_LIMIT (1u << 24)
 
 #define PH_SSA 0
 #define PH_E1 1
@@ -591,7 +599,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
                 if (!(lambda > 0.0))
                     break; /* nothing can happen: time moves to T */
                 if (k == OR_STEP_LIMIT) {
-                    bad = OR_E_BAD_RATE;
+                    bad = OR_E_STEP_LIMIT;
                     break;
                 }
                 uint32_t r[4];

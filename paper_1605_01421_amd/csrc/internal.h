@@ -81,6 +81,29 @@ __host__ __device__ inline size_t rec_index(int m, int c, int k, int width, int 
            (size_t)(k - nmajor);
 }
 
+// Workgroups are handed to the device's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  One-lane-per-node wavefronts store
+// a day's record of a compartment as pack consecutive 4-byte words, less
+// than a 128-byte cache line when pack < 32; neighbouring wavefronts on
+// different XCDs would then write parts of one line from several L2s.  From
+// the first whole round of XCDs after the wide nodes' workgroups (a, a
+// multiple of 8) on, workgroups are renumbered in spans of 8 g: XCD x takes
+// g consecutive ones, which together fill whole lines, while the spans still
+// rotate over all XCDs (neighbouring chunks have similar work: the nodes are
+// ordered by it).  A bijection: workgroups outside whole spans keep their
+// number.
+constexpr int XCDS = 8;
+__host__ __device__ inline int xcd_block(int b, int b0, int nblk, int g) {
+    if (g <= 1) return b;  // (g is 0 when a wavefront's records already fill lines)
+    const int a = (b0 + XCDS - 1) / XCDS * XCDS;
+    const int span = XCDS * g;
+    const int full_end = nblk > a ? a + (nblk - a) / span * span : a;
+    if (b < a || b >= full_end) return b;
+    const int r = b - a;
+    const int rem = r % span;
+    return a + (r - rem) + (rem % XCDS) * g + rem / XCDS;
+}
+
 struct KParams {
     int32_t n;        // nodes in the group
     int32_t nb;       // number of unit-time steps

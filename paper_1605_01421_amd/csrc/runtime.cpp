@@ -80,6 +80,8 @@ struct siminf_model {
     long long sums_len = 0;
     int32_t* d_pos = nullptr;
     hipStream_t last_stream = nullptr;
+    void* stage = nullptr;  // siminf_trajectory's device staging for host copies
+    size_t stage_bytes = 0;
     bool pending = false, ran = false;
     int status = 0;
     int32_t err_code = 0, err_phase = -1, err_run = -1;
@@ -956,50 +958,54 @@ int siminf_trajectory(siminf_model* m, int32_t run, int32_t* U, double* V, int32
     if (!m || run < 0 || run >= m->R) return SIMINF_E_ARG;
     if (m->record != SIMINF_RECORD_FULL) return SIMINF_E_ARG;
     if (!m->ran) return SIMINF_E_ARG;
-    finish(m);
+    const int status = finish(m);
+    if (status == SIMINF_E_DEVICE) return status;
     const RunInfo& ri = m->runs[run];
     const Group& g = m->groups[ri.group];
     const int nc = g.shape.nc, nv = g.shape.nv;
     const size_t nU = (size_t)m->ntspan * ri.nn * nc, nV = (size_t)m->ntspan * ri.nn * nv;
-    if (ri.nn == 0) return SIMINF_OK;
+    if (ri.nn == 0) return status;
     int32_t* dU = nullptr;
     double* dV = nullptr;
-    bool tmpU = false, tmpV = false;
-    if (U) {
-        if (dst_is_device) dU = U;
-        else if (hipMalloc((void**)&dU, sizeof(int32_t) * nU) != hipSuccess) return SIMINF_E_ALLOC;
-        else tmpU = true;
+    if (!dst_is_device) {
+        // one staging buffer per handle, grown to the largest request
+        const size_t need = sizeof(int32_t) * (U ? nU : 0) + sizeof(double) * ((V && nv > 0) ? nV : 0) + 16;
+        if (need > m->stage_bytes) {
+            if (m->stage) (void)hipFree(m->stage);
+            m->stage = nullptr;
+            m->stage_bytes = 0;
+            if (hipMalloc(&m->stage, need) != hipSuccess) return SIMINF_E_ALLOC;
+            m->stage_bytes = need;
+        }
+        char* base = (char*)m->stage;
+        dV = (V && nv > 0) ? (double*)base : nullptr;
+        dU = U ? (int32_t*)(base + ((V && nv > 0) ? sizeof(double) * nV : 0)) : nullptr;
+    } else {
+        dU = U;
+        dV = nv > 0 ? V : nullptr;
     }
-    if (V && nv > 0) {
-        if (dst_is_device) dV = V;
-        else if (hipMalloc((void**)&dV, sizeof(double) * nV) != hipSuccess) {
-            if (tmpU) (void)hipFree(dU);
-            return SIMINF_E_ALLOC;
-        } else tmpV = true;
-    }
-    int rc = SIMINF_OK;
-    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, g.p.nmajor, m->d_pos + ri.noff, ri.nn, dU, dV, nullptr) !=
+    hipStream_t st = m->last_stream;
+    if (launch_gather(nc, nv, g.p.U, g.p.V, g.n, m->ntspan, g.p.nmajor, m->d_pos + ri.noff, ri.nn, dU, dV, st) !=
             hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess)
-        rc = SIMINF_E_DEVICE;
-    if (rc == SIMINF_OK && tmpU && hipMemcpy(U, dU, sizeof(int32_t) * nU, hipMemcpyDeviceToHost) != hipSuccess)
-        rc = SIMINF_E_DEVICE;
-    if (rc == SIMINF_OK && tmpV && hipMemcpy(V, dV, sizeof(double) * nV, hipMemcpyDeviceToHost) != hipSuccess)
-        rc = SIMINF_E_DEVICE;
-    if (tmpU) (void)hipFree(dU);
-    if (tmpV) (void)hipFree(dV);
-    return rc;
+        hipStreamSynchronize(st) != hipSuccess)
+        return SIMINF_E_DEVICE;
+    if (!dst_is_device) {
+        if (U && hipMemcpy(U, dU, sizeof(int32_t) * nU, hipMemcpyDeviceToHost) != hipSuccess) return SIMINF_E_DEVICE;
+        if (dV && hipMemcpy(V, dV, sizeof(double) * nV, hipMemcpyDeviceToHost) != hipSuccess) return SIMINF_E_DEVICE;
+    }
+    return status;
 }
 
 int siminf_sums(siminf_model* m, int64_t* sums, int32_t dst_is_device) {
     if (!m || !sums || m->record != SIMINF_RECORD_SUMS || !m->ran) return SIMINF_E_ARG;
-    finish(m);
+    const int status = finish(m);
+    if (status == SIMINF_E_DEVICE) return status;
     const size_t bytes = sizeof(int64_t) * (size_t)m->sums_len;
-    if (bytes == 0) return SIMINF_OK;
+    if (bytes == 0) return status;
     if (hipMemcpy(sums, m->d_sums, bytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost) !=
         hipSuccess)
         return SIMINF_E_DEVICE;
-    return SIMINF_OK;
+    return status;
 }
 
 int siminf_counters(siminf_model* m, uint64_t out[4]) {
@@ -1029,6 +1035,41 @@ int siminf_error_info(const siminf_model* m, int32_t* code, int64_t* step, int32
     if (index) *index = m->err_index;
     if (run) *run = m->err_run;
     return SIMINF_OK;
+}
+
+int siminf_error_message(const siminf_model* m, char* buf, size_t cap) {
+    if (!m || !buf || cap == 0) return SIMINF_E_ARG;
+    static const char* const phases[] = {"the SSA", "a node-local event", "an external transfer",
+                                         "the post-time step"};
+    const char* what = "";
+    switch (m->err_code) {
+        case SIMINF_E_NEG_STATE: what = "a transition made a compartment negative"; break;
+        case SIMINF_E_BAD_RATE: what = "a transition rate was negative or not finite"; break;
+        case SIMINF_E_EVENT_OVERDRAW: what = "an event asked for more individuals than the selected compartments hold"; break;
+        case SIMINF_E_EVENT_INDEX: what = "an event names a node, select column or shift out of range"; break;
+        case SIMINF_E_PTS: what = "the post-time-step function produced a non-finite state"; break;
+        case SIMINF_E_STEP_LIMIT: what = "a node needed more than 2^24 SSA draws in one unit of time"; break;
+        case SIMINF_E_DEVICE: what = "a HIP runtime error, or a wait inside a kernel passed its time limit"; break;
+        case SIMINF_E_ARG: what = "an invalid argument or model"; break;
+        case SIMINF_E_UNSUPPORTED: what = "a model or size the library does not implement"; break;
+        case SIMINF_E_ALLOC: what = "an allocation failed"; break;
+        default: break;
+    }
+    int n;
+    if (m->err_code == 0) {
+        n = std::snprintf(buf, cap, "SIMINF_OK");
+    } else if (m->err_phase >= 0 && m->err_phase <= 3) {
+        const bool node_phase = m->err_phase == PH_SSA || m->err_phase == PH_PTS;
+        n = std::snprintf(buf, cap, "%s at day step %lld in %s, %s %lld of run %d: %s",
+                          siminf_status_string(m->err_code), (long long)m->err_step, phases[m->err_phase],
+                          node_phase ? "node" : "event", (long long)m->err_index, m->err_run, what);
+    } else if (m->err_index >= 0) {
+        n = std::snprintf(buf, cap, "%s at create, event %lld: %s", siminf_status_string(m->err_code),
+                          (long long)m->err_index, what);
+    } else {
+        n = std::snprintf(buf, cap, "%s: %s", siminf_status_string(m->err_code), what);
+    }
+    return n < 0 ? SIMINF_E_ARG : SIMINF_OK;
 }
 
 int siminf_launch_info(const siminf_model* m, int32_t out[8]) {
@@ -1167,6 +1208,7 @@ void siminf_destroy(siminf_model* m) {
         if (e) (void)hipEventDestroy(e);
     drop_graph(m);
     if (m->h_rp) (void)hipHostFree(m->h_rp);
+    if (m->stage) (void)hipFree(m->stage);
     for (void* p : m->owned) (void)hipFree(p);
     delete m;
 }
@@ -1183,6 +1225,7 @@ const char* siminf_status_string(int32_t code) {
         case SIMINF_E_EVENT_OVERDRAW: return "SIMINF_E_EVENT_OVERDRAW";
         case SIMINF_E_EVENT_INDEX: return "SIMINF_E_EVENT_INDEX";
         case SIMINF_E_PTS: return "SIMINF_E_PTS";
+        case SIMINF_E_STEP_LIMIT: return "SIMINF_E_STEP_LIMIT";
     }
     return "SIMINF_UNKNOWN";
 }

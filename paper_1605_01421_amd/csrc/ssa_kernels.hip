@@ -30,11 +30,16 @@ namespace siminf {
 
 namespace {
 
-constexpr int E_NEG_STATE = -5, E_BAD_RATE = -6, E_OVERDRAW = -7, E_PTS = -9;
+constexpr int E_NEG_STATE = -5, E_BAD_RATE = -6, E_OVERDRAW = -7, E_PTS = -9, E_STEP_LIMIT = -10;
 constexpr int EV_EXIT = 0, EV_ENTER = 1, EV_EXTTRANS = 3;
 
-// Transitions of one node within one unit of time beyond which the rates are
-// declared unusable (time would no longer advance at binary64 resolution).
+// Implementation limit on the draws of one node within one unit of time (the
+// method itself has none).  The draw index is the first Philox counter word,
+// so a node-day has 2^32 distinct blocks; the library stops far earlier so
+// that a node with exploding rates ends the run (E_STEP_LIMIT, keyed like any
+// SSA error) instead of holding its lane for hours.  A node that needs the
+// draw with index STEP_LIMIT fails; every node-day with fewer draws is the
+// method's own result.
 constexpr uint32_t STEP_LIMIT = 1u << 24;
 
 __device__ __forceinline__ void raise_error(Ctrl* c, int step, int phase, int64_t ord, int code) {
@@ -145,7 +150,7 @@ __device__ __forceinline__ int ssa_to_boundary(const KParams& p, Node<M>& s, dou
     if (!(lam > 0.0)) return 0;
     StepRandoms cur = step_randoms(k0, k1, 0u, day_word, node, tag);
     for (uint32_t step = 0;;) {
-        if (step == STEP_LIMIT) return E_BAD_RATE;
+        if (step == STEP_LIMIT) return E_STEP_LIMIT;
         draws += 1;
         StepRandoms nxt{0.0, 0.0};
         if constexpr (PIPE) nxt = step_randoms(k0, k1, step + 1u, day_word, node, tag);
@@ -204,7 +209,7 @@ __device__ __forceinline__ int ssa_wide(const KParams& p, Node<M>& s, double t, 
     if (!(lam > 0.0)) return 0;
     const unsigned long long one = lane == 0 ? 1ull : 0ull;
     for (uint32_t base = 0;; base += WAVE) {
-        if (base >= STEP_LIMIT) return E_BAD_RATE;
+        if (base >= STEP_LIMIT) return E_STEP_LIMIT;
         const StepRandoms mine = step_randoms(k0, k1, base + (uint32_t)lane, day_word, node, tag);
         for (int i = 0; i < WAVE; ++i) {
             const double e = read_lane(mine.e, i);
@@ -428,12 +433,12 @@ __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double 
         int kend, aend;
         bool done = true;
         if (kl < LAT_W && kl <= kc && kl <= kf) {
-            // the draw with index STEP_LIMIT: the node's rates are unusable
+            // the draw with index STEP_LIMIT: the implementation limit
             kend = kl;
             aend = __builtin_amdgcn_readlane(pa, kl);
             nd += (uint32_t)kl;
             ntr += (uint32_t)kl;
-            rc = E_BAD_RATE;
+            rc = E_STEP_LIMIT;
         } else if (kc <= kf && kc < LAT_W) {
             // stops at the boundary before the transition of step kc
             kend = kc;
@@ -573,7 +578,7 @@ __device__ __forceinline__ int ssa_group(const KParams& p, Node<M>& s, bool live
             const bool draw = !stop && !bad && !lim;
             const double tn = t + tk[k];
             const bool go = draw && !(tn >= T);
-            rc = bad ? ((ck[k] & 1) ? E_NEG_STATE : (ck[k] & 2) ? E_BAD_RATE : 0) : lim ? E_BAD_RATE : rc;
+            rc = bad ? ((ck[k] & 1) ? E_NEG_STATE : (ck[k] & 2) ? E_BAD_RATE : 0) : lim ? E_STEP_LIMIT : rc;
             nd += draw ? 1u : 0u;
             t = go ? tn : t;
             kapp += go ? 1 : 0;
@@ -887,28 +892,6 @@ __device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long
 #pragma unroll
         for (int c = 0; c < NC; ++c) u[c] += p.mail_big[(size_t)e * MAX_NC + c];
     }
-}
-
-// Workgroups are handed to the device's 8 XCDs in turn (workgroup b to XCD
-// b mod 8), and each XCD has its own L2.  One-lane-per-node wavefronts store
-// a day's record of a compartment as pack consecutive 4-byte words, less
-// than a 128-byte cache line when pack < 32; neighbouring wavefronts on
-// different XCDs would then write parts of one line from several L2s.  From
-// the first whole round of XCDs after the wide nodes' workgroups (a, a
-// multiple of 8) on, workgroups are renumbered in spans of 8 g: XCD x takes
-// g consecutive ones, which together fill whole lines, while the spans still
-// rotate over all XCDs (neighbouring chunks have similar work: the nodes are
-// ordered by it).  A bijection: workgroups outside whole spans keep their
-// number.
-constexpr int XCDS = 8;
-__device__ __forceinline__ int xcd_block(int b, int b0, int nblk, int g) {
-    const int a = (b0 + XCDS - 1) / XCDS * XCDS;
-    const int span = XCDS * g;
-    const int full_end = nblk > a ? a + (nblk - a) / span * span : a;
-    if (g <= 1 || b < a || b >= full_end) return b;
-    const int r = b - a;
-    const int rem = r % span;
-    return a + (r - rem) + (rem % XCDS) * g + rem / XCDS;
 }
 
 template <class M, bool PIPE, bool GRP>

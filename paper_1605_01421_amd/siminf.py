@@ -7,8 +7,11 @@ missing -- there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -18,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libsiminf.so")
 SIMINF_OK = 0
 STATUS = {0: "SIMINF_OK", -1: "SIMINF_E_ARG", -2: "SIMINF_E_UNSUPPORTED", -3: "SIMINF_E_ALLOC",
           -4: "SIMINF_E_DEVICE", -5: "SIMINF_E_NEG_STATE", -6: "SIMINF_E_BAD_RATE",
-          -7: "SIMINF_E_EVENT_OVERDRAW", -8: "SIMINF_E_EVENT_INDEX", -9: "SIMINF_E_PTS"}
+          -7: "SIMINF_E_EVENT_OVERDRAW", -8: "SIMINF_E_EVENT_INDEX", -9: "SIMINF_E_PTS",
+          -10: "SIMINF_E_STEP_LIMIT"}
 RECORD_FULL, RECORD_SUMS = 0, 1
 
 
@@ -62,6 +66,7 @@ SIGNATURES = {
     "siminf_counters": (ctypes.c_int, [_P, _P]),
     "siminf_shape": (ctypes.c_int, [_P, _P]),
     "siminf_error_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "siminf_error_message": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "siminf_launch_info": (ctypes.c_int, [_P, _P]),
     "siminf_timing": (ctypes.c_int, [_P, _P]),
     "siminf_autotune": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, _P, _P]),
@@ -85,6 +90,19 @@ SIGNATURES = {
 }
 
 _lib = None
+
+# Handles still open are closed by an exit hook while the HIP runtime is
+# certainly alive, rather than by __del__ during interpreter teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
 
 
 def load():
@@ -200,6 +218,7 @@ class Model:
         lib.siminf_shape(self._h, _ptr(shape))
         self.runs, self.total_nodes, self.ntspan, self.ncmax, self.nvmax, self.n_steps = (int(x) for x in shape)
         self.run_spec = [k for k, r in enumerate(self.replicates) for _ in range(r)]
+        _live.add(self)
 
     # -- lifecycle ---------------------------------------------------------
     def close(self):
@@ -208,6 +227,8 @@ class Model:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return  # the process is ending: the device memory goes with it
         try:
             self.close()
         except Exception:
@@ -238,8 +259,10 @@ class Model:
         run = ctypes.c_int32()
         self._lib.siminf_error_info(self._h, ctypes.byref(code), ctypes.byref(step), ctypes.byref(phase),
                                     ctypes.byref(index), ctypes.byref(run))
+        buf = ctypes.create_string_buffer(256)
+        self._lib.siminf_error_message(self._h, buf, len(buf))
         return dict(code=code.value, name=STATUS.get(code.value, str(code.value)), step=step.value,
-                    phase=phase.value, index=index.value, run=run.value)
+                    phase=phase.value, index=index.value, run=run.value, message=buf.value.decode())
 
     def counters(self) -> dict:
         out = np.zeros(4, dtype=np.uint64)
@@ -342,6 +365,7 @@ class MLP:
         if rc != SIMINF_OK:
             raise SiminfError(rc, "siminf_mlp_create")
         self.max_batch = int(max_batch)
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -349,6 +373,8 @@ class MLP:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return  # the process is ending: the device memory goes with it
         try:
             self.close()
         except Exception:

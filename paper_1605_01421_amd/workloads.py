@@ -277,6 +277,67 @@ def sir_with_events(seed: int = 1, Nn: int = 10_000, days: int = 365) -> ModelSp
                     name=f"sir-events-{Nn}x{days}")
 
 
+def sir_with_shifts(seed: int = 5, Nn: int = 600, days: int = 60, heavy: int = 8) -> ModelSpec:
+    """SIR with every kind of scheduled event and the select / shift
+    machinery of Table 2 in use: births as in ``sir_with_events``, external
+    transfers of a proportion of {S, I, R}, and
+
+    * internal transfers (a vaccination-like move, as in section 5.1.2):
+      select {S, I}, shift column 0 = (+2, +1, 0) (S -> R, I -> R), a
+      proportion of the selected total (n = 0) or a fixed n;
+    * shifted external transfers: select {S, I}, shift column 1 =
+      (+1, +1, 0) (an S individual arrives in the destination's I, an I in
+      its R), given as a proportion or as a fixed n;
+    * exits given as a proportion (n = 0);
+    * enter events into a select column with two rows, {I, R}: the
+      individuals go to the first selected compartment, I;
+    * same-node external transfers (source equals destination).
+
+    The first ``heavy`` nodes are large (thousands of individuals), so that
+    launches that give the heaviest nodes a wavefront or a group of lanes
+    apply these events there too.  Proportions never overdraw and fixed
+    counts are sized from the generator's running totals."""
+    rng = np.random.default_rng(seed)
+    size = np.clip(np.round(rng.lognormal(np.log(80.0), 1.0, Nn)), 1, 3000).astype(np.int64)
+    size[:heavy] = rng.integers(4000, 9000, heavy)
+    I0 = np.maximum(np.round(0.02 * size), 1).astype(np.int64)
+    u0 = np.stack([size - I0, I0, np.zeros(Nn, np.int64)], axis=1).astype(np.int32)
+    # births (fixed counts into S); every removal below is a proportion, or a
+    # small fixed count from a heavy node, so that no event can overdraw
+    base = _demographic_events(rng, Nn, size, days, birth=0.001, exit_=0.0,
+                               ship_frac=0.0, select_all=3, birth_select=0)
+    rows = []
+    for t in range(1, days + 1):
+        # plain external transfers of a proportion of {S, I, R}
+        for node in rng.choice(Nn, size=max(1, Nn // 60), replace=False):
+            rows.append((EXTTRANS, t, int(node), int(rng.integers(0, Nn)), 0, float(rng.uniform(0.01, 0.3)), 3, -1))
+        # internal transfers: a proportion of {S, I}, or a fixed small n
+        for node in rng.choice(Nn, size=max(1, Nn // 40), replace=False):
+            rows.append((INTTRANS, t, int(node), 0, 0, float(rng.uniform(0.05, 0.5)), 4, 0))
+        rows.append((INTTRANS, t, int(rng.integers(0, heavy)), 0, int(rng.integers(1, 6)), 0.0, 4, 0))
+        # shifted external transfers by proportion, some to the node itself
+        for node in rng.choice(Nn, size=max(1, Nn // 60), replace=False):
+            dest = int(node) if rng.random() < 0.1 else int(rng.integers(0, Nn))
+            rows.append((EXTTRANS, t, int(node), dest, 0, float(rng.uniform(0.01, 0.2)), 4, 1))
+        # a heavy node ships a fixed count with the shift
+        h = int(rng.integers(0, heavy))
+        rows.append((EXTTRANS, t, h, int(rng.integers(0, Nn)), int(rng.integers(1, 4)), 0.0, 4, 1))
+        # proportional exits, and enters into the {I, R} column
+        for node in rng.choice(Nn, size=max(1, Nn // 50), replace=False):
+            rows.append((EXIT, t, int(node), 0, 0, float(rng.uniform(0.0, 0.1)), 3, -1))
+        for node in rng.choice(Nn, size=max(1, Nn // 80), replace=False):
+            rows.append((ENTER, t, int(node), 0, int(rng.integers(1, 3)), 0.0, 5, -1))
+    ev = concat_events(base, make_events(rows))
+    S, G, _, _ = sir_matrices()
+    E = np.array([[1, 0, 0, 1, 1, 0],
+                  [0, 1, 0, 1, 1, 1],
+                  [0, 0, 1, 1, 0, 1]], dtype=np.int32)
+    N = np.array([[2, 1], [1, 1], [0, 0]], dtype=np.int32)
+    spec = sir_spec(u0, np.arange(0, days + 1), 0.16, 0.077, events=ev, name=f"sir-shifts-{Nn}x{days}")
+    spec.E, spec.N = E, N
+    return spec
+
+
 def sise_with_events(seed: int = 2, Nn: int = 37_000, days: int = 3650) -> ModelSpec:
     """SISe with events: lognormal sizes (median 40, sigma 0.39, about 1.6M
     individuals for 37,000 nodes), 10% of nodes start with floor(5% of S)

@@ -456,3 +456,49 @@ def test_split_run_equals_full_run(lib):
     S1, S1V = go(W.sise_spec(su, np.arange(0, 41), 0.02, 0.1, 1.0, bq), 3, 0)
     S2, S2V = go(W.sise_spec(S1[-1], np.arange(40, 91), 0.02, 0.1, 1.0, bq, phi0=S1V[-1, :, 0]), 3, 0)
     assert np.array_equal(F[40:], S2) and np.array_equal(FV[40:], S2V)
+
+
+def _without_transfers(spec):
+    keep = np.asarray(spec.events["event"]) != W.EXTTRANS
+    ev = {k: np.asarray(v)[keep] for k, v in spec.events.items()}
+    out = W.sir_spec(np.asarray(spec.u0), np.asarray(spec.tspan), 0.16, 0.077, events=ev,
+                     name=spec.name + "-no-transfers")
+    out.E, out.N = spec.E, spec.N
+    return out
+
+
+@pytest.mark.parametrize("opts", [dict(mode=1), dict(mode=2, lanes=1), dict(mode=2, lanes=64, wide=8),
+                                  dict(mode=2, lanes=1, group=-1), dict(mode=2, lanes=64, wide=8, group=-1),
+                                  dict(mode=2, lanes=64, wide=8, group=-1, lattice=2)])
+def test_internal_and_shifted_transfers(lib, opts):
+    """Section 3.3 and Table 2 on the GPU: internal transfers with the shift
+    matrix N (proportional and fixed counts), shifted external transfers,
+    proportional exits and transfers (n = 0), enters into a two-row select
+    column and transfers from a node to itself, in the grid-barrier and the
+    dataflow kernels, with the heaviest nodes on a wavefront or on a group of
+    lanes; bit-exact against the oracle (state, counters)."""
+    spec = W.sir_with_shifts(seed=6)
+    m, ref, rc = _run_both(lib, spec, 29, 2, **opts)
+    assert rc == 0 and ref["status"] == 0
+    info = m.launch_info()
+    assert info["mode"] == opts["mode"], info
+    if opts["mode"] == 2 and opts.get("lanes") == 64:
+        assert info["wide"] == 8, info
+    _compare(m, ref, what=f"shifts {opts}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
+@pytest.mark.parametrize("opts", [dict(lanes=1), dict(lanes=64, wide=8), dict(lanes=1, group=-1),
+                                  dict(lanes=64, wide=8, group=-1)])
+def test_internal_transfers_free_running(lib, opts):
+    """The same events without the external transfers, in the free-running
+    kernel: internal transfers with shifts applied by one lane, a wavefront
+    or a group of lanes, bit-exact against the oracle."""
+    spec = _without_transfers(W.sir_with_shifts(seed=7))
+    m, ref, rc = _run_both(lib, spec, 31, 9, **opts)
+    assert rc == 0 and ref["status"] == 0
+    assert m.launch_info()["mode"] == 0
+    _compare(m, ref, what=f"internal transfers {opts}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])

@@ -64,11 +64,54 @@ def test_gradients_match_central_differences():
 
 def test_first_adamw_step_is_sign_step():
     params = [(np.array([[1.0, -2.0]]), np.array([0.5]))]
-    grads = [(np.array([[0.3, -4.0]]), np.array([0.0]))]
+    grads = [(np.array([[0.3, -4.0]]), np.array([0.25]))]
     st = mlp.init_state(params)
-    mlp.adamw_step(params, grads, st, lr=0.01, eps=0.0, weight_decay=0.1)
+    mlp.adamw_step(params, grads, st, lr=0.01, eps=1e-12, weight_decay=0.1)
     # m_hat = g, v_hat = g^2 on the first step -> update lr * (sign(g) + wd * w)
-    assert np.allclose(params[0][0], [[1.0 - 0.01 * (1 + 0.1), -2.0 - 0.01 * (-1 + 0.1 * -2.0)]])
+    assert np.allclose(params[0][0], [[1.0 - 0.01 * (1 + 0.1), -2.0 - 0.01 * (-1 + 0.1 * -2.0)]], rtol=1e-12)
+    assert np.allclose(params[0][1], [0.5 - 0.01 * (1 + 0.1 * 0.5)], rtol=1e-12)
+
+
+@pytest.mark.parametrize("beta1,beta2,eps", [(0.9, 0.999, 1e-8), (0.5, 0.7, 0.3)])
+def test_adamw_constant_gradient_closed_form(beta1, beta2, eps):
+    """With the same gradient g at every step, the bias-corrected moments are
+    exactly m_hat = g and v_hat = g^2 at every t (that is what the
+    corrections 1 - beta^t are for), so each step is the linear map
+    w <- a w - c with a = 1 - lr wd and c = lr g / (|g| + eps), and
+    w_t = a^t w_0 - c (1 - a^t) / (1 - a).  A wrong exponent in either
+    correction, a missing eps or decay, breaks this at t >= 2."""
+    lr, wd, T = 0.05, 0.2, 7
+    g = np.array([[0.3, -4.0, 1e-3]])
+    w0 = np.array([[1.0, -2.0, 0.7]])
+    params = [(w0.copy(), np.array([0.0]))]
+    st = mlp.init_state(params)
+    a = 1.0 - lr * wd
+    c = lr * g / (np.abs(g) + eps)
+    for t in range(1, T + 1):
+        mlp.adamw_step(params, [(g, np.array([0.0]))], st, lr=lr, beta1=beta1, beta2=beta2, eps=eps,
+                       weight_decay=wd)
+        want = a ** t * w0 - c * (1.0 - a ** t) / (1.0 - a)
+        assert np.allclose(params[0][0], want, rtol=1e-11, atol=1e-14), t
+        assert np.all(np.isfinite(params[0][1]))
+    assert st["t"] == T
+
+
+def test_adamw_moments_after_gradient_stops():
+    """After t steps of gradient g and one step of gradient 0 (no decay), the
+    corrected first moment is beta1 (1 - beta1^t) / (1 - beta1^(t+1)) g and the
+    second beta2 (1 - beta2^t) / (1 - beta2^(t+1)) g^2: the step is
+    lr m_hat / (sqrt(v_hat) + eps)."""
+    b1, b2, eps, lr, t = 0.8, 0.95, 1e-3, 0.1, 4
+    g = np.array([[2.0, -0.5]])
+    params = [(np.zeros((1, 2)), np.array([0.0]))]
+    st = mlp.init_state(params)
+    for _ in range(t):
+        mlp.adamw_step(params, [(g, np.array([0.0]))], st, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    before = params[0][0].copy()
+    mlp.adamw_step(params, [(np.zeros_like(g), np.array([0.0]))], st, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    mh = b1 * (1 - b1 ** t) / (1 - b1 ** (t + 1)) * g
+    vh = b2 * (1 - b2 ** t) / (1 - b2 ** (t + 1)) * g * g
+    assert np.allclose(before - params[0][0], lr * mh / (np.sqrt(vh) + eps), rtol=1e-12)
 
 
 def test_bf16_rounding_matches_torch():

@@ -137,6 +137,42 @@ def test_sir_matches_master_equation(orc, N, S0, I0, beta, gamma):
         assert _chi2_pooled(obs, P * n) > 1e-4
 
 
+def _sis_master_equation(N, I0, beta, gamma, times):
+    """SIS chain on I = 0..N with S = N - I (the population is closed): the
+    infection S + I -> 2I at beta S I and the recovery I -> S at gamma I
+    (eqs. sirtrans, SIRstoich), P(t) = expm(Q t) P0."""
+    Q = np.zeros((N + 1, N + 1))
+    for i in range(N + 1):
+        r_inf = beta * (N - i) * i
+        r_rec = gamma * i
+        if r_inf > 0:
+            Q[i + 1, i] += r_inf
+            Q[i, i] -= r_inf
+        if r_rec > 0:
+            Q[i - 1, i] += r_rec
+            Q[i, i] -= r_rec
+    P0 = np.zeros(N + 1)
+    P0[I0] = 1.0
+    return [linalg.expm(Q * t) @ P0 for t in times]
+
+
+@pytest.mark.parametrize("N,I0,beta,gamma", [(20, 3, 0.05, 0.6), (9, 1, 0.4, 0.9)])
+def test_sis_matches_master_equation(orc, N, I0, beta, gamma):
+    """P4 for the SIS rates: the law of I of the SIS SSA against the
+    brute-force master-equation solution (a dropped factor, a swapped rate or
+    a wrong column of S changes the law)."""
+    n = 100_000
+    times = [1.0, 3.0, 10.0]
+    spec = W.sis_spec(np.tile([N - I0, I0], (n, 1)), [0.0] + times, beta, gamma)
+    r = orc.run(spec, seed=4242, stream=5)
+    assert r["status"] == 0
+    for m, P in enumerate(_sis_master_equation(N, I0, beta, gamma, times), start=1):
+        U = r["U"][m]
+        assert (U.sum(axis=1) == N).all()
+        obs = np.bincount(U[:, 1], minlength=N + 1)
+        assert _chi2_pooled(obs, P * n) > 1e-4
+
+
 def test_sir_large_population_follows_ode(orc):
     """P9: for large N the mean trajectory follows dx/dt = S R(x) (eq. ODE)."""
     Npop, I0, n = 100_000, 1000, 8
@@ -255,16 +291,25 @@ def test_split_run_equals_full_run(orc):
     assert np.array_equal(fa["U"][40:], s2["U"]) and np.array_equal(fa["V"][40:], s2["V"])
 
 
-def test_step_guard(orc):
-    """Immigration without death: X(1) ~ Poisson(kappa) exactly.  Below the
-    2^24-draw guard the count is Poisson (within 6 sd); above it the node
-    stops with E_BAD_RATE at the first day step, keyed to node 0."""
+def test_step_limit(orc):
+    """The implementation limit of 2^24 draws per node-day.  Immigration
+    without death: X(1) ~ Poisson(kappa) exactly, and every draw of the day
+    but the last is a transition.  Below the limit the count is Poisson
+    (within 6 sd).  Above it the node has made exactly 2^24 transitions (draws
+    0 .. 2^24 - 1) when it would need draw 2^24, and the run stops with
+    E_STEP_LIMIT (not a rate error: the rates are valid), keyed to day step 0,
+    phase SSA, node 0; node 1 (same rates) is not reached in the key order."""
     ok = W.birth_death_spec(np.array([0]), [0.0, 1.0], 1.0e7, 0.0, immigration=True)
     r = orc.run(ok, seed=4, stream=0, nthreads=1)
     assert r["status"] == 0
     x = int(r["U"][-1, 0, 0])
     assert abs(x - 1.0e7) < 6 * np.sqrt(1.0e7)
-    big = W.birth_death_spec(np.array([0, 0]), [0.0, 1.0], 3.0e7, 0.0, immigration=True)
-    r = orc.run(big, seed=4, stream=0, nthreads=2)
-    assert r["status"] == -6                      # E_BAD_RATE
-    assert r["error"] == (-6, 0, 0, 0)            # (code, day step, phase SSA, node 0)
+    assert r["transitions"] == x
+    big = W.birth_death_spec(np.array([0]), [0.0, 1.0], 3.0e7, 0.0, immigration=True)
+    r = orc.run(big, seed=4, stream=0, nthreads=1)
+    assert r["status"] == -10                     # E_STEP_LIMIT
+    assert r["error"] == (-10, 0, 0, 0)           # (code, day step, phase SSA, node 0)
+    assert r["transitions"] == 2 ** 24
+    two = W.birth_death_spec(np.array([0, 0]), [0.0, 1.0], 3.0e7, 0.0, immigration=True)
+    r = orc.run(two, seed=4, stream=0, nthreads=2)
+    assert r["error"] == (-10, 0, 0, 0)
