@@ -146,16 +146,18 @@ def build_workload(name):
 
 
 def cpu_baseline_batch(batch, seed, seconds, gpu_sums):
-    """The oracle on a sample of a batch's runs, one replicate of each
-    parameter set in a seeded shuffled order of the sets (run r uses stream
-    r), until the time budget is spent; the weekly sums of every sampled run
-    are checked against the GPU's."""
+    """The oracle on a sample of a batch's runs: one replicate of each
+    parameter set in a seeded shuffled order of the sets, then another
+    replicate of each, and so on (run r uses stream r), until the time budget
+    is spent; the weekly sums of every sampled run are checked against the
+    GPU's."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
     flat = [spec for spec, reps in batch for _ in range(reps)]
     starts = np.cumsum([0] + [reps for _, reps in batch])[:-1]
     order = np.random.default_rng(7).permutation(len(batch))
-    sample = [int(starts[s] + (s % batch[s][1])) for s in order]
+    sample = [int(starts[s] + (s + j) % batch[s][1]) for j in range(max(r for _, r in batch)) for s in order
+              if j < batch[s][1]]
     runs, node_days, t_total, parity = 0, 0, 0.0, True
     for r in sample:
         if t_total >= seconds:
@@ -168,8 +170,8 @@ def cpu_baseline_batch(batch, seed, seconds, gpu_sums):
         node_days += out["node_days"]
         runs += 1
     return {"value": node_days / t_total, "unit": "node-days/s", "cores": threads, "kind": "oracle",
-            "sample": f"{runs} of the batch's {len(flat)} runs (one replicate each of {runs} parameter sets, "
-                      f"seed {seed}), {node_days} node-days in {t_total:.1f} s of CPU time",
+            "sample": f"{runs} of the batch's {len(flat)} runs (replicates of all {len(batch)} parameter sets in "
+                      f"turn, seed {seed}), {node_days} node-days in {t_total:.1f} s of CPU time",
             "sums_match_gpu": parity}
 
 
@@ -270,6 +272,9 @@ def main():
     ap.add_argument("--pack", type=int, default=0, help="nodes per one-lane-per-node wavefront: 0 auto, 4, 8, 16, 32, 64")
     ap.add_argument("--group", type=int, default=0,
                     help="nodes after the wide ones on a group of 8 lanes: 0 none/tuned, -1 all, N")
+    ap.add_argument("--lane-queue", type=int, default=0,
+                    help="runs without transfers: 1 every lane advances its own node, 2 lanes in lockstep, 0 auto")
+    ap.add_argument("--chunk", type=int, default=0, help="lane queue: nodes per chunk (0 auto)")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the run from a captured HIP graph: 1 on, 0 off, -1 on for batches without transfers")
     ap.add_argument("--no-cpu", action="store_true")
@@ -298,7 +303,8 @@ def main():
     graph = args.graph if args.graph >= 0 else int(batch)
     model = siminf.Model(spec, record=siminf.RECORD_SUMS if batch else siminf.RECORD_FULL, block=args.block,
                          order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline,
-                         pack=args.pack, graph=graph, group=args.group)
+                         pack=args.pack, graph=graph, group=args.group, lane_queue=args.lane_queue,
+                         chunk=args.chunk)
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
@@ -346,8 +352,8 @@ def main():
     draws_per_launch = draws / args.steps
     achieved = draws_per_launch * OPS_PER_STEP / mean_kernel_s
     info = model.launch_info()
-    traffic_bytes, traffic_launch = measured_traffic_at(["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
-                                                        desc["workload"])
+    kernel_name = ["free_kernel", "sync_kernel", "flow_kernel", "lane_kernel"][info["mode"]]
+    traffic_bytes, traffic_launch = measured_traffic_at(kernel_name, desc["workload"])
     out = {
         "metric": METRIC,
         "value": node_days / wall,
@@ -362,7 +368,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(desc, seed=seed0, block=info["block"], blocks=info["blocks"],
-                       kernel=["free-running", "grid-barrier", "dataflow"][info["mode"]],
+                       kernel=["free-running", "grid-barrier", "dataflow", "lane-queue"][info["mode"]],
+                       chunk=info["chunk"],
                        wide_nodes=info["wide"], pipeline=info["pipeline"], pack=info["pack"],
                        group_nodes=info["group"], graph=graph),
         "transitions_per_s": transitions / wall,
@@ -374,7 +381,7 @@ def main():
                      "traffic": traffic_bytes,
                      # the counters' launch shape: the autotuner may pick another one from run to run
                      "traffic_launch": traffic_launch,
-                     "kernel": ["free_kernel", "sync_kernel", "flow_kernel"][info["mode"]],
+                     "kernel": kernel_name,
                      "ssa_steps_per_launch": draws_per_launch, "ops_per_step": OPS_PER_STEP},
     }
     alg = algorithmic_bytes(spec, batch)

@@ -173,6 +173,19 @@ typedef struct {
                           that many.  Only where the lattice walk applies (see
                           lattice) and not in the grid-barrier kernel; the
                           results do not depend on it. */
+    int32_t lane_queue;/* models without external transfers: 1 every node on one
+                          lane that advances its node day by day on its own and,
+                          when the node is done, takes the next node of its
+                          wavefront's chunk (the throughput kernel); 2 off (the
+                          lanes of a wavefront go through each day together);
+                          0 auto: on when no lanes, wide, group or pack option
+                          is set and the model has at least 64 nodes per SIMD
+                          of the device.  With SIMINF_RECORD_SUMS it needs
+                          2 x Ntspan x Nc x 8 bytes of LDS per wavefront (at
+                          most 64 KiB per workgroup), else SIMINF_E_UNSUPPORTED
+                          (auto: off).  The results do not depend on it. */
+    int32_t chunk;     /* lane queue: nodes per chunk (consecutive nodes of one
+                          run handed to one wavefront), 64..1048576; 0 = 512 */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;
@@ -271,11 +284,12 @@ int siminf_error_message(const siminf_model *m, char *buf, size_t cap);
 
 /* Launch configuration chosen for the handle (its first model group):
  * out[0] threads per block, out[1] blocks, out[2] kernel (0 free-running,
- * 1 grid-barrier, 2 dataflow), out[3] pipelining on/off, out[4] order,
- * out[5] nodes carried by a whole wavefront, out[6] nodes per wavefront of
- * the one-lane-per-node ones (the pack option), out[7] nodes on a group of
- * lanes (the group option). */
-int siminf_launch_info(const siminf_model *m, int32_t out[8]);
+ * 1 grid-barrier, 2 dataflow, 3 lane queue), out[3] pipelining on/off,
+ * out[4] order, out[5] nodes carried by a whole wavefront, out[6] nodes per
+ * wavefront of the one-lane-per-node ones (the pack option), out[7] nodes
+ * on a group of lanes (the group option), out[8] lane queue: nodes per
+ * chunk (0 = not the lane queue), out[9] dynamic LDS bytes per workgroup. */
+int siminf_launch_info(const siminf_model *m, int32_t out[10]);
 
 /* Autotuner: runs the model `repeats` times for each candidate launch shape
  * (threads per block 64/128/256; no wavefront-wide nodes, or those whose

@@ -159,14 +159,26 @@ struct KParams {
     int32_t lattice;             // wide nodes walk a lattice of reachable states
     uint64_t wait_ticks;         // wall-clock ticks one wait may last before abort
     const RunParams* rp;         // seed and stream base of the current run (device)
+    int32_t lane_queue;          // free-running, one lane per node, each lane advancing its
+                                 // own node and taking the next node of its chunk when done
+    int32_t nlchunks;            // lane-queue chunks (runs cut into pieces of consecutive nodes)
+    const int4* lchunks;         // [nlchunks] x = first node, y = end, z = run
+    int32_t lq_batch;            // lanes that wait at their day's end before the
+                                 // wavefront closes their days together
 };
+
+// Lane-queue kernel: recording slots per wavefront (a slot accumulates one
+// chunk's per-run sums in LDS) and the LDS budget of a workgroup for them.
+constexpr int LQ_SLOTS = 2;
+constexpr int LQ_LDS_BYTES = 64 * 1024;
 
 // Launchers implemented in ssa_kernels.hip.
 hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st);
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem,
                         hipStream_t st);
-int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem);
+int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem,
+                      bool lane_queue = false);
 hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nmajor,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
 hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,

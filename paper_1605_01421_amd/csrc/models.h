@@ -33,6 +33,8 @@ struct ModelSIR {
                                                int64_t) {
         return true;
     }
+    // the post-time step leaves every state unchanged
+    __device__ static __forceinline__ bool pts_fixed(const double*, const int32_t*) { return true; }
 };
 
 // SIS (eqs. sirtrans, SIRstoich): S + I -> 2I at beta S I; I -> S at gamma I.
@@ -50,6 +52,8 @@ struct ModelSIS {
                                                int64_t) {
         return true;
     }
+    // the post-time step leaves every state unchanged
+    __device__ static __forceinline__ bool pts_fixed(const double*, const int32_t*) { return true; }
 };
 
 // SISe (section 4.2 without the spatial coupling term): S -> I at upsilon phi
@@ -86,6 +90,11 @@ struct ModelSISe {
         v[0] = phi;
         return isfinite(phi);
     }
+    // states the post-time step maps to themselves bit for bit: phi = +0 with
+    // no infected (kept = +0 (1 - beta) is +0 or -0, shed = +0, the sum +0)
+    __device__ static __forceinline__ bool pts_fixed(const double* v, const int32_t* u) {
+        return __double_as_longlong(v[0]) == 0 && u[1] == 0;
+    }
 };
 
 // Linear birth-death: X -> 2X at b X, X -> 0 at d X.  gdata = (b, d).
@@ -100,6 +109,8 @@ struct ModelBirthDeath {
                                                int64_t) {
         return true;
     }
+    // the post-time step leaves every state unchanged
+    __device__ static __forceinline__ bool pts_fixed(const double*, const int32_t*) { return true; }
 };
 
 // Immigration-death: 0 -> X at kappa, X -> 0 at mu X.  gdata = (kappa, mu).
@@ -117,6 +128,8 @@ struct ModelImmigrationDeath {
                                                int64_t) {
         return true;
     }
+    // the post-time step leaves every state unchanged
+    __device__ static __forceinline__ bool pts_fixed(const double*, const int32_t*) { return true; }
 };
 
 // Host-side table of model shapes.

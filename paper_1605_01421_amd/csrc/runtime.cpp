@@ -40,6 +40,11 @@ struct Group {
     KParams p{};
     int64_t n_e1 = 0, n_e2 = 0, n_levels = 0;
     std::vector<int64_t> work;  // expected work of each node, internal (descending) order
+    std::vector<int32_t> node_run;  // run of each node, internal order (lane-queue chunks)
+    int4* d_chunks = nullptr;       // lane-queue chunk table and its capacity
+    int chunk_cap = 0;
+    int lq_chunk = 0;               // lane queue: nodes per chunk (0 = off)
+    int lq_batch = 0;               //             lanes per day-end batch
 };
 
 template <class T>
@@ -224,9 +229,91 @@ int default_group(const Group& g, int nbig, int div) {
 // Kernel and launch shape of one group.  want_mode applies to groups with
 // external transfers: 0 auto (dataflow if every node wavefront fits on the
 // device at once, else grid barrier), 1 barrier, 2 dataflow.
-int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode, int pack, int ngrp) {
+// LDS a lane-queue workgroup of wpb wavefronts needs: the day-to-record
+// table (nb + 1 ints, padded to 8 bytes), and per wavefront its recording
+// slots, the slots' global data and its counters.
+size_t lane_queue_lds(const siminf_model* m, const Group& g, int wpb) {
+    const size_t table = (size_t)(m->nb + 2) / 2 * sizeof(uint64_t);
+    const size_t slots = m->record == SIMINF_RECORD_SUMS ? (size_t)LQ_SLOTS * m->ntspan * g.shape.nc : 0;
+    // per wavefront: recording slots, each slot's global data, four counters
+    return table + (size_t)wpb * (slots + (size_t)LQ_SLOTS * g.shape.ngd + 4) * sizeof(uint64_t);
+}
+
+// Kernel and launch shape of one group.  want_mode applies to groups with
+// external transfers: 0 auto (dataflow if every node wavefront fits on the
+// device at once, else grid barrier), 1 barrier, 2 dataflow.  lq_chunk > 0
+// (groups without external transfers): the lane-queue kernel with chunks of
+// that many nodes; nbig, pack and ngrp are then ignored.
+int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int want_mode, int pack, int ngrp,
+              int lq_chunk, int lq_batch = 16) {
     drop_graph(m);
     KParams& p = g.p;
+    p.lane_queue = 0;
+    g.lq_chunk = 0;
+    if (lq_chunk > 0 && g.n_e2 == 0) {
+        const int cus = device_cus(m);
+        if (cus <= 0) return SIMINF_E_DEVICE;
+        if (block == 0) block = 256;
+        const int wpb = block / WAVE;
+        const size_t lds = lane_queue_lds(m, g, wpb);
+        if (lds > (size_t)LQ_LDS_BYTES) return SIMINF_E_UNSUPPORTED;
+        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, 0, false, block, lds, true);
+        if (per_cu <= 0) return SIMINF_E_DEVICE;
+        // chunks: consecutive nodes of one run, at most lq_chunk of them and,
+        // past a wavefront's worth of nodes, at most 1/8 of one wavefront's
+        // share of the expected work, so that the chunks a wavefront still
+        // works on at the end of the run are short
+        long double total = 0;
+        for (int64_t w : g.work) total += (long double)w;
+        const long double budget = total / ((long double)per_cu * cus * wpb * 8.0L);
+        std::vector<int4> ch;
+        for (int k = 0; k < g.n;) {
+            int e = k + 1;
+            long double w = (long double)g.work[k];
+            while (e < g.n && e - k < lq_chunk && g.node_run[e] == g.node_run[k] &&
+                   (e - k < WAVE || w + g.work[e] <= budget)) {
+                w += (long double)g.work[e];
+                ++e;
+            }
+            ch.push_back(make_int4(k, e, g.node_run[k], 0));
+            k = e;
+        }
+        if ((int)ch.size() > g.chunk_cap) {
+            // more pieces than the table holds: the table's size was set for
+            // chunks of at least 64 nodes; grow it
+            void* grown = nullptr;
+            if (hipMalloc(&grown, sizeof(int4) * ch.size()) != hipSuccess) return SIMINF_E_ALLOC;
+            m->owned.push_back(grown);
+            g.d_chunks = (int4*)grown;
+            g.chunk_cap = (int)ch.size();
+        }
+        if (!ch.empty() && hipMemcpy(g.d_chunks, ch.data(), sizeof(int4) * ch.size(), hipMemcpyHostToDevice) !=
+                               hipSuccess)
+            return SIMINF_E_DEVICE;
+        int blocks = std::max(1, std::min(per_cu * cus, ((int)ch.size() + wpb - 1) / wpb));
+        if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
+        g.mode = MODE_FREE;
+        p.mode = MODE_FREE;
+        p.lane_queue = 1;
+        p.nlchunks = (int)ch.size();
+        p.lchunks = g.d_chunks;
+        p.pipeline = 0;
+        p.nbig = 0;
+        p.pack = WAVE;
+        p.ngrp = 0;
+        p.ngw = 0;
+        p.nmajor = 0;
+        p.nchunks = 0;
+        g.block = block;
+        g.blocks = blocks;
+        g.shmem = lds;
+        g.lq_chunk = lq_chunk;
+        g.lq_batch = std::max(1, std::min(lq_batch, WAVE));
+        p.lq_batch = g.lq_batch;
+        p.nblocks = blocks;
+        return SIMINF_OK;
+    }
+    if (lq_chunk > 0) return SIMINF_E_UNSUPPORTED;
     const int n = g.n;
     const int cus = device_cus(m);
     if (cus <= 0) return SIMINF_E_DEVICE;
@@ -324,6 +411,11 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
     if ((m->opt.pack != 0 && m->opt.pack != 4 && m->opt.pack != 8 && m->opt.pack != 16 && m->opt.pack != 32 &&
          m->opt.pack != 64) ||
         m->opt.group < -1) {
+        set_create_error(m, SIMINF_E_ARG, -1, -1);
+        return SIMINF_E_ARG;
+    }
+    if (m->opt.lane_queue < 0 || m->opt.lane_queue > 2 || (m->opt.chunk != 0 && (m->opt.chunk < 64 ||
+                                                                               m->opt.chunk > (1 << 20)))) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -789,9 +881,27 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 alloc_device(m->owned, (size_t)p.n_e2 * MAX_NC, &p.mail_big))
                 return hip_fail(m);
         }
+        g.node_run = node_run;
+        int lq = 0;
+        if (g.n_e2 == 0) {
+            // the lane-queue chunk table: at most one chunk per run and per 64 nodes more
+            g.chunk_cap = (int)grp_runs.size() + n / 64 + 1;
+            if (alloc_device(m->owned, (size_t)g.chunk_cap, &g.d_chunks)) return hip_fail(m);
+            const int chunk = m->opt.chunk > 0 ? m->opt.chunk : 512;
+            const bool shaped = m->opt.lanes != 0 || m->opt.wide != 0 || m->opt.group != 0 || m->opt.pack != 0;
+            const int wpb = (m->opt.block ? m->opt.block : 256) / WAVE;
+            if (m->opt.lane_queue == 1)
+                lq = chunk;
+            else if (m->opt.lane_queue == 0 && !shaped && (int64_t)n >= (int64_t)cus * 4 * WAVE &&
+                     lane_queue_lds(m, g, wpb) <= (size_t)LQ_LDS_BYTES)
+                lq = chunk;
+        } else if (m->opt.lane_queue == 1) {
+            set_create_error(m, SIMINF_E_UNSUPPORTED, -1, -1);
+            return SIMINF_E_UNSUPPORTED;
+        }
         const int nb = default_wide(m, g);
         const int rc = configure(m, g, m->opt.block, nb, m->opt.pipeline, m->opt.mode, m->opt.pack,
-                                 m->opt.group < 0 ? g.n : m->opt.group);
+                                 m->opt.group < 0 ? g.n : m->opt.group, lq);
         if (rc) {
             set_create_error(m, rc, -1, -1);
             return rc;
@@ -1072,21 +1182,21 @@ int siminf_error_message(const siminf_model* m, char* buf, size_t cap) {
     return n < 0 ? SIMINF_E_ARG : SIMINF_OK;
 }
 
-int siminf_launch_info(const siminf_model* m, int32_t out[8]) {
+int siminf_launch_info(const siminf_model* m, int32_t out[10]) {
     if (!m || !out) return SIMINF_E_ARG;
-    if (m->groups.empty()) {
-        for (int i = 0; i < 8; ++i) out[i] = 0;
-        return SIMINF_OK;
-    }
+    for (int i = 0; i < 10; ++i) out[i] = 0;
+    if (m->groups.empty()) return SIMINF_OK;
     const Group& g = m->groups[0];
     out[0] = g.block;
     out[1] = g.blocks;
-    out[2] = g.mode;
+    out[2] = g.p.lane_queue ? 3 : g.mode;
     out[3] = g.p.pipeline;
     out[4] = m->opt.order;
     out[5] = g.p.nbig;
     out[6] = g.p.pack;
     out[7] = g.p.ngrp;
+    out[8] = g.lq_chunk;
+    out[9] = (int32_t)g.shmem;
     return SIMINF_OK;
 }
 
@@ -1096,6 +1206,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     finish(m);
     struct Cand {
         int block, wide_div, pipeline, pack, grp_div;  // grp_div: see default_group (-1: none)
+        int lq;                                        // lane queue: nodes per chunk (0: off)
+        int lqb = 16;                                  //             lanes per day-end batch
     };
     auto groups_of = [&](const Group& g, int nb, int gdiv) {
         if (m->opt.group != 0) return m->opt.group < 0 ? g.n : (int)m->opt.group;
@@ -1106,8 +1218,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     auto measure = [&](const Cand& c) -> double {
         for (Group& g : m->groups) {
             const int nb = default_wide(m, g, c.wide_div);
-            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode, c.pack, groups_of(g, nb, c.grp_div)) !=
-                SIMINF_OK)
+            if (configure(m, g, c.block, nb, c.pipeline, m->opt.mode, c.pack, groups_of(g, nb, c.grp_div), c.lq,
+                          c.lqb) != SIMINF_OK)
                 return -1.0;
         }
         std::vector<double> t;
@@ -1123,9 +1235,21 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     };
     const int pack0 = m->opt.pack ? m->opt.pack : WAVE;
     std::vector<Cand> cands;
-    for (int block : {64, 128, 256})
-        for (int div : {0, 4, 16, 64})  // wide nodes: none, or work above 1/div of the heaviest
-            for (int pipe : {1, 2}) cands.push_back({block, div, pipe, pack0, -1});
+    if (m->opt.lane_queue != 1)
+        for (int block : {64, 128, 256})
+            for (int div : {0, 4, 16, 64})  // wide nodes: none, or work above 1/div of the heaviest
+                for (int pipe : {1, 2}) cands.push_back({block, div, pipe, pack0, -1, 0});
+    // the lane queue (models without external transfers), at three block
+    // sizes and two chunk sizes, unless an option fixes the lane layout
+    bool free_only = true;
+    for (const Group& g : m->groups) free_only = free_only && g.n_e2 == 0;
+    const bool shaped = m->opt.lanes != 0 || m->opt.wide != 0 || m->opt.group != 0 || m->opt.pack != 0;
+    if (free_only && m->opt.lane_queue != 2 && (m->opt.lane_queue == 1 || !shaped)) {
+        const int ch = m->opt.chunk > 0 ? m->opt.chunk : 512;
+        for (int block : {64, 128, 256})
+            for (int lqb : {4, 8, 16}) cands.push_back({block, 0, 2, WAVE, -1, ch, lqb});
+    }
+    if (cands.empty()) return SIMINF_E_UNSUPPORTED;
     double best = 1e300;
     Cand pick = cands[0];
     bool any = false;
@@ -1134,8 +1258,10 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     auto consider = [&](const Cand& c) {
         const double t = measure(c);
         if (log) {
-            std::fprintf(stderr, "siminf_autotune: block %d wide_div %d pipeline %d pack %d group_div %d: %.3f ms\n",
-                         c.block, c.wide_div, c.pipeline, c.pack, c.grp_div, t);
+            std::fprintf(stderr,
+                         "siminf_autotune: block %d wide_div %d pipeline %d pack %d group_div %d lane_queue %d/%d: "
+                         "%.3f ms\n",
+                         c.block, c.wide_div, c.pipeline, c.pack, c.grp_div, c.lq, c.lqb, t);
             std::fflush(stderr);
         }
         if (t >= 0.0 && t < best) {
@@ -1153,13 +1279,13 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     // is then tuned again, since cheaper narrow nodes move its optimum.
     long long lanes_needed = 0;
     for (const Group& g : m->groups) lanes_needed += g.n;
-    if (m->opt.pack == 0 && (lanes_needed + WAVE - 1) / WAVE < (long long)device_cus(m) * 4) {
+    if (pick.lq == 0 && m->opt.pack == 0 && (lanes_needed + WAVE - 1) / WAVE < (long long)device_cus(m) * 4) {
         const Cand first = pick;
-        for (int pack : {32, 16, 8, 4}) consider({first.block, first.wide_div, first.pipeline, pack, -1});
+        for (int pack : {32, 16, 8, 4}) consider({first.block, first.wide_div, first.pipeline, pack, -1, 0});
         if (pick.pack != first.pack) {
             const Cand second = pick;
             for (int div : {0, 4, 16, 64})
-                if (div != second.wide_div) consider({second.block, div, second.pipeline, second.pack, -1});
+                if (div != second.wide_div) consider({second.block, div, second.pipeline, second.pack, -1, 0});
         }
         // then the heaviest nodes after the wide ones on groups of lanes (the
         // lattice walk on GROUP_LANES lanes): an eighth, a quarter, half or
@@ -1173,7 +1299,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
                 for (int pk : {16, 8})
                     if (pk != third.pack) packs.push_back(pk);
             for (int pack : packs)
-                for (int gdiv : {8, 4, 2, 1}) consider({third.block, third.wide_div, third.pipeline, pack, gdiv});
+                for (int gdiv : {8, 4, 2, 1})
+                    consider({third.block, third.wide_div, third.pipeline, pack, gdiv, 0});
         }
         // pipelining was chosen on the first sweep's shape: try the other
         // setting on the final one
@@ -1183,7 +1310,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     }
     for (Group& g : m->groups) {
         const int nb = default_wide(m, g, pick.wide_div);
-        configure(m, g, pick.block, nb, pick.pipeline, m->opt.mode, pick.pack, groups_of(g, nb, pick.grp_div));
+        configure(m, g, pick.block, nb, pick.pipeline, m->opt.mode, pick.pack, groups_of(g, nb, pick.grp_div),
+                  pick.lq, pick.lqb);
     }
     if (best_ms) *best_ms = best;
     return SIMINF_OK;

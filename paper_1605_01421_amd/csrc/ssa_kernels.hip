@@ -111,21 +111,28 @@ struct Transition {
 // for recomputation.  err: E_NEG_STATE if a compartment went negative, else
 // E_BAD_RATE if a recomputed rate is negative or not finite, else 0.
 template <class M>
-__device__ __forceinline__ Transition<M> transition(const KParams& p, const Node<M>& s, double w0, double w1,
-                                                    double x) {
+__device__ __forceinline__ Transition<M> transition_of(const KParams& p, const int32_t* u, const double* v,
+                                                       const double* ld, const double* gd, double w0, double w1,
+                                                       double x) {
     Transition<M> r;
     const int n = (w0 > 0.0 && x <= w0) ? 0 : (w1 > 0.0 ? 1 : 0);
     bool neg = false;
 #pragma unroll
     for (int c = 0; c < M::NC; ++c) {
-        r.u[c] = s.u[c] + (n ? p.S[c + M::NC] : p.S[c]);
+        r.u[c] = u[c] + (n ? p.S[c + M::NC] : p.S[c]);
         neg |= r.u[c] < 0;
     }
     const uint32_t g = n ? p.Gmask[1] : p.Gmask[0];
-    r.w0 = (g & 1u) ? M::template rate<0>(r.u, s.v, s.ld, s.gd) : w0;
-    r.w1 = (g & 2u) ? M::template rate<1>(r.u, s.v, s.ld, s.gd) : w1;
+    r.w0 = (g & 1u) ? M::template rate<0>(r.u, v, ld, gd) : w0;
+    r.w1 = (g & 2u) ? M::template rate<1>(r.u, v, ld, gd) : w1;
     r.err = neg ? E_NEG_STATE : (rate_ok(r.w0) && rate_ok(r.w1)) ? 0 : E_BAD_RATE;
     return r;
+}
+
+template <class M>
+__device__ __forceinline__ Transition<M> transition(const KParams& p, const Node<M>& s, double w0, double w1,
+                                                    double x) {
+    return transition_of<M>(p, s.u, s.v, s.ld, s.gd, w0, w1, x);
 }
 
 // Direct-method SSA of one node from time t to the day boundary T
@@ -857,6 +864,325 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
 }
 
 // ---------------------------------------------------------------------------
+// lane-queue kernel (no external transfers, one lane per node, lanes advance
+// independently)
+// ---------------------------------------------------------------------------
+// In free_kernel a wavefront's nodes go through each day together, so a day
+// costs the wavefront as many steps as its busiest node needs that day, and
+// a node whose epidemic has died out keeps its lane to the end.  Here every
+// lane advances its own node: an iteration draws one step for each lane
+// that is inside a day, and a lane whose step crosses its day boundary (or
+// whose day has no positive rate) closes that day -- node-local events,
+// post-time step, records -- and opens the next one.  A lane whose node has
+// finished its last day takes the next node of its wavefront's chunk
+// (consecutive nodes of one run, heaviest first); the wavefront takes a new
+// chunk from the work queue when its chunk has been handed out.  A node
+// that can no longer change (every rate zero, no event left, a state the
+// post-time step maps to itself) is finished at once: its state is recorded
+// for every remaining tspan point.  Per-run sums are accumulated per chunk
+// in LDS (a wavefront holds at most LQ_SLOTS chunks) and added to the global
+// sums when the chunk's last node is done.  Each node goes through exactly
+// the operations of ssa_to_boundary and day_events, so every result is
+// bit-identical to the other kernels'.
+// Per-lane state of the lane-queue kernel.  The run's global data sit in the
+// lane's LDS slot, and the counters in LDS per wavefront, to leave the
+// registers to the SSA.
+template <class M>
+struct LaneState {
+    int32_t u[M::NC];
+    double v[M::NV > 0 ? M::NV : 1];
+    double ld[M::NLD > 0 ? M::NLD : 1];
+    int k = -1;  // node, -1 when the lane is free
+    int slot = 0, b = 0, cur = 0, cend = 0;
+    int etime = 0;      // time of the node's next node-local event
+    bool open = false;  // inside a day with lambda > 0: the next draw is due
+    uint32_t node = 0, tag = 0, step = 0;
+    uint32_t dd = 0, dt = 0;  // draws and transitions of the current day
+    double t = 0.0, T = 0.0, w0 = 0.0, w1 = 0.0, lam = 0.0;
+};
+
+// Counters of a wavefront in LDS: transitions, node-days, events, draws.
+enum { LQ_TR = 0, LQ_ND = 1, LQ_EV = 2, LQ_DR = 3, LQ_TALLIES = 4 };
+
+// Records the state at the tspan indices [m0, m1): into the lane's LDS slot
+// (sums) or the trajectory buffer.
+template <class M>
+__device__ __forceinline__ void lane_record(const KParams& p, const LaneState<M>& L, unsigned long long* slotbase,
+                                            int m0, int m1) {
+    for (int m = m0; m < m1; ++m) {
+        if (p.record != 0) {
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c)
+                atomicAdd(slotbase + m * M::NC + c, (unsigned long long)(int64_t)L.u[c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) p.U[rec_index(m, c, L.k, M::NC, p.ntspan, p.n, 0)] = L.u[c];
+#pragma unroll
+            for (int c = 0; c < M::NV; ++c) p.V[rec_index(m, c, L.k, M::NV, p.ntspan, p.n, 0)] = L.v[c];
+        }
+    }
+}
+
+// Ends the lane's node after an error of `phase` at its current day.
+template <class M>
+__device__ __forceinline__ void lane_fail(const KParams& p, LaneState<M>& L, int phase, int64_t ord, int code,
+                                          unsigned long long* tally) {
+    raise_error(p.ctrl, L.b, phase, ord, code);
+    atomicAdd(tally + LQ_DR, (unsigned long long)L.dd);
+    atomicAdd(tally + LQ_TR, (unsigned long long)L.dt);
+    atomicAdd(tally + LQ_ND, 1ull);
+    L.k = -1;
+    L.open = false;
+}
+
+// Opens day b of the lane's node: all rates from the state (Appendix A, a
+// new unit of time), lambda, and whether a draw is due.  A node whose rates
+// are all zero with no event left and a fixed point of the post-time step
+// is finished here, its state recorded for the rest of the run.
+template <class M>
+__device__ __forceinline__ void lane_open_day(const KParams& p, LaneState<M>& L, unsigned long long* slotbase,
+                                              const double* gd, const int* rec_off, unsigned long long* tally) {
+    L.T = (double)(p.T1 + L.b);
+    L.t = L.b == 0 ? p.t0 : L.T - 1.0;
+    L.step = 0;
+    L.dd = 0;
+    L.dt = 0;
+    L.w0 = M::template rate<0>(L.u, L.v, L.ld, gd);
+    L.w1 = M::template rate<1>(L.u, L.v, L.ld, gd);
+    if (!rate_ok(L.w0) || !rate_ok(L.w1)) {
+        lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], E_BAD_RATE, tally);
+        return;
+    }
+    double lam = 0.0;
+    lam = lam + L.w0;
+    lam = lam + L.w1;
+    L.lam = lam;
+    L.open = lam > 0.0;
+    if (!L.open && L.cur >= L.cend && M::pts_fixed(L.v, L.u)) {
+        lane_record<M>(p, L, slotbase, rec_off[L.b], p.ntspan);
+        atomicAdd(tally + LQ_ND, (unsigned long long)(p.nb - L.b));
+        L.k = -1;
+    }
+}
+
+// Loads node k (of the run `run`) into a free lane.
+template <class M>
+__device__ __forceinline__ void lane_load(const KParams& p, LaneState<M>& L, int k, int slot, int run,
+                                          uint32_t stream_base) {
+    L.k = k;
+    L.slot = slot;
+#pragma unroll
+    for (int c = 0; c < M::NC; ++c) L.u[c] = p.u0[(size_t)c * p.n + k];
+#pragma unroll
+    for (int c = 0; c < M::NV; ++c) L.v[c] = p.v0[(size_t)c * p.n + k];
+#pragma unroll
+    for (int l = 0; l < M::NLD; ++l) L.ld[l] = p.ld[(size_t)l * p.n + k];
+    L.node = (uint32_t)p.node_idx[k];
+    L.tag = (stream_base + (uint32_t)run) & 0xFFFFFFu;
+    L.cur = p.e1_off[k];
+    L.cend = p.e1_off[k + 1];
+    L.etime = L.cur < L.cend ? p.e1.rec[L.cur].x : 0;
+    L.b = 0;
+}
+
+template <class M>
+__global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
+    extern __shared__ unsigned long long lq_lds[];
+    const KParams& p = pa;
+    const uint64_t seed = p.rp->seed;
+    const uint32_t stream_base = p.rp->stream_base;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    const bool sums = p.record != 0;
+    const int per_slot = sums ? p.ntspan * M::NC : 0;
+    // LDS: the tspan indices recorded after each day (read at every day's
+    // end), then per wavefront its recording slots, its slots' global data
+    // and its counters
+    int* rec_off = (int*)lq_lds;
+    for (int i = threadIdx.x; i <= p.nb; i += blockDim.x) rec_off[i] = p.rec_off[i];
+    const int per_wave = LQ_SLOTS * per_slot + LQ_SLOTS * M::NGD + LQ_TALLIES;
+    unsigned long long* mine = lq_lds + (p.nb + 2) / 2 + (size_t)(threadIdx.x / WAVE) * per_wave;
+    double* gdl = (double*)(mine + LQ_SLOTS * per_slot);
+    unsigned long long* tally = mine + LQ_SLOTS * per_slot + LQ_SLOTS * M::NGD;
+    for (int i = lane; i < per_wave; i += WAVE) mine[i] = 0ull;
+    __syncthreads();
+    // wavefront-uniform: the run of each slot (-1 free), the chunk being handed out
+    int srun0 = -1, srun1 = -1;
+    int cslot = -1, next = 0, stop = 0;
+    bool drained = false;
+    LaneState<M> L;
+    // adds a slot's sums to the global ones and clears it
+    auto flush = [&](int sl, int r) {
+        unsigned long long* base = mine + sl * per_slot;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < per_slot; i += WAVE) {
+            const unsigned long long v = base[i];
+            if (v) atomicAdd(p.sums + ((size_t)r * p.ntspan + i / M::NC) * p.sums_nc + i % M::NC, v);
+            base[i] = 0ull;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+    for (unsigned round = 0;; ++round) {
+        // the first error's day: nodes past it stop (their later records are
+        // undefined); refreshed every 8 rounds
+        if ((round & 7u) == 0) {
+            uint64_t key = 0;
+            if (lane == 0) key = __hip_atomic_load(&p.ctrl->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t err_day = __shfl(key, 0, WAVE) >> 44;
+            if (L.k >= 0 && (uint64_t)L.b > err_day) {
+                L.k = -1;
+                L.open = false;
+            }
+        }
+        // ---- free lanes: finished chunks are flushed, new nodes handed out
+        unsigned long long freem = __ballot(L.k < 0);
+        if (freem) {
+            if (srun0 >= 0 && !(cslot == 0 && next < stop) && !__ballot(L.k >= 0 && L.slot == 0)) {
+                if (sums) flush(0, srun0);
+                srun0 = -1;
+                if (cslot == 0) cslot = -1;
+            }
+            if (srun1 >= 0 && !(cslot == 1 && next < stop) && !__ballot(L.k >= 0 && L.slot == 1)) {
+                if (sums) flush(1, srun1);
+                srun1 = -1;
+                if (cslot == 1) cslot = -1;
+            }
+            while (freem) {
+                if (cslot < 0 || next >= stop) {
+                    const int fs = srun0 < 0 ? 0 : srun1 < 0 ? 1 : -1;
+                    if (drained || fs < 0) break;
+                    unsigned c = 0;
+                    if (lane == 0) c = atomicAdd(&p.ctrl->work[p.group], 1u);
+                    c = __shfl(c, 0, WAVE);
+                    if (c >= (unsigned)p.nlchunks) {
+                        drained = true;
+                        break;
+                    }
+                    const int4 ch = p.lchunks[c];
+                    cslot = fs;
+                    if (fs == 0)
+                        srun0 = ch.z;
+                    else
+                        srun1 = ch.z;
+                    next = ch.x;
+                    stop = ch.y;
+                    // the run's global data into the slot (the slot is free:
+                    // no lane reads it)
+                    if (lane < M::NGD) gdl[fs * M::NGD + lane] = p.gdata[(size_t)p.run_spec[ch.z] * p.ngd + lane];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+                const int take = min(__popcll(freem), stop - next);
+                const int rank = __popcll(freem & lt_mask);
+                const bool me = ((freem >> lane) & 1ull) && rank < take;
+                if (me) {
+                    lane_load<M>(p, L, next + rank, cslot, cslot == 0 ? srun0 : srun1, stream_base);
+                    lane_open_day<M>(p, L, mine + L.slot * per_slot, gdl + L.slot * M::NGD, rec_off, tally);
+                }
+                next += take;
+                freem &= ~__ballot(me);
+            }
+        }
+        if (!__ballot(L.k >= 0)) {
+            if (drained) break;
+            continue;
+        }
+        // ---- draws: one step of ssa_to_boundary's loop for every lane inside
+        // a day, until lq_batch lanes wait at the end of a day or have no node
+        // (or no lane has a draw due); those are then served together
+        for (;;) {
+            if (L.open) {
+                if (L.step == STEP_LIMIT) {
+                    lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], E_STEP_LIMIT, tally);
+                } else {
+                    L.dd += 1;
+                    const StepRandoms r =
+                        step_randoms(k0, k1, L.step, (uint32_t)(int32_t)(p.T1 + L.b), L.node, L.tag);
+                    const double tau = r.e / L.lam;
+                    const double tn = L.t + tau;
+                    const Transition<M> nx =
+                        transition_of<M>(p, L.u, L.v, L.ld, gdl + L.slot * M::NGD, L.w0, L.w1, L.lam * r.r2);
+                    if (tn >= L.T) {
+                        L.open = false;
+                    } else {
+                        L.t = tn;
+#pragma unroll
+                        for (int c = 0; c < M::NC; ++c) L.u[c] = nx.u[c];
+                        L.w0 = nx.w0;
+                        L.w1 = nx.w1;
+                        L.dt += 1;
+                        if (nx.err) {
+                            lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], nx.err, tally);
+                        } else {
+                            double lam = 0.0;
+                            lam = lam + L.w0;
+                            lam = lam + L.w1;
+                            L.lam = lam;
+                            if (!(lam > 0.0))
+                                L.open = false;
+                            else
+                                ++L.step;
+                        }
+                    }
+                }
+            }
+            const unsigned long long idle = __ballot(!L.open);
+            if (__popcll(idle) >= (unsigned)p.lq_batch || idle == ~0ull) break;
+        }
+        // ---- day end: node-local events, post-time step, records, next day
+        if (L.k >= 0 && !L.open) {
+            const double* gd = gdl + L.slot * M::NGD;
+            unsigned long long* slotbase = mine + L.slot * per_slot;
+            atomicAdd(tally + LQ_DR, (unsigned long long)L.dd);
+            atomicAdd(tally + LQ_TR, (unsigned long long)L.dt);
+            L.dd = 0;
+            L.dt = 0;
+            bool dead = false;
+            while (L.cur < L.cend && (double)L.etime <= L.T) {
+                const int rc = apply_event<M::NC>(p.e1.rec[L.cur], p.e1.prop, L.cur, seed, L.tag, L.u, L.u);
+                if (rc) {
+                    lane_fail<M>(p, L, PH_E1, p.e1.ordinal[L.cur], rc, tally);
+                    dead = true;
+                    break;
+                }
+                atomicAdd(tally + LQ_EV, 1ull);
+                ++L.cur;
+                if (L.cur < L.cend) L.etime = p.e1.rec[L.cur].x;
+            }
+            if (!dead && !M::pts(L.v, L.u, L.ld, gd, p.T1 + L.b)) {
+                lane_fail<M>(p, L, PH_PTS, p.node_ord[L.k], E_PTS, tally);
+                dead = true;
+            }
+            if (!dead) {
+                atomicAdd(tally + LQ_ND, 1ull);
+                lane_record<M>(p, L, slotbase, rec_off[L.b], rec_off[L.b + 1]);
+                L.b += 1;
+                if (L.b >= p.nb)
+                    L.k = -1;
+                else
+                    lane_open_day<M>(p, L, slotbase, gd, rec_off, tally);
+            }
+        }
+    }
+    // nodes finished at once in the last hand-out may have left records in a slot
+    if (sums) {
+        if (srun0 >= 0) flush(0, srun0);
+        if (srun1 >= 0) flush(1, srun1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        for (int i = 0; i < LQ_TALLIES; ++i) {
+            const unsigned long long v = tally[i];
+            if (v) atomicAdd(&p.ctrl->counters[i == LQ_TR ? 0 : i == LQ_ND ? 1 : i == LQ_EV ? 2 : 3], v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // dataflow kernel (external transfers, every node resident)
 // ---------------------------------------------------------------------------
 constexpr unsigned long long MAIL_PACKED = 1ull << 63;  // counts packed in bits 0..47
@@ -1250,17 +1576,18 @@ const void* kernel_for(int mode, bool grp) {
 }
 
 template <class M>
-const void* kernel_for(int mode, int pipeline, bool grp) {
+const void* kernel_for(int mode, int pipeline, bool grp, bool lq) {
+    if (mode == MODE_FREE && lq) return (const void*)lane_kernel<M>;
     return pipeline ? kernel_for<M, true>(mode, grp) : kernel_for<M, false>(mode, grp);
 }
 
-const void* model_kernel(int model, int mode, int pipeline, bool grp) {
+const void* model_kernel(int model, int mode, int pipeline, bool grp, bool lq) {
     switch (model) {
-        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline, grp);
-        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline, grp);
-        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline, grp);
-        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline, grp);
-        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline, grp);
+        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline, grp, lq);
+        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline, grp, lq);
+        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline, grp, lq);
+        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline, grp, lq);
+        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline, grp, lq);
     }
     return nullptr;
 }
@@ -1277,7 +1604,7 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
 }
 
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st) {
-    const void* fn = model_kernel(model, p.mode, p.pipeline, p.ngrp > 0);
+    const void* fn = model_kernel(model, p.mode, p.pipeline, p.ngrp > 0, p.lane_queue != 0);
     if (!fn) return hipErrorInvalidValue;
     KParams arg = p;
     void* args[] = {&arg};
@@ -1285,8 +1612,8 @@ hipError_t launch_group(int model, const KParams& p, int block, int blocks, size
     return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(block), args, (unsigned)shmem, st);
 }
 
-int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem) {
-    const void* fn = model_kernel(model, mode, pipeline, grp);
+int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem, bool lane_queue) {
+    const void* fn = model_kernel(model, mode, pipeline, grp, lane_queue);
     int n = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, shmem) != hipSuccess) return 0;
     return n;

@@ -502,3 +502,96 @@ def test_internal_transfers_free_running(lib, opts):
     _compare(m, ref, what=f"internal transfers {opts}")
     c = m.counters()
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
+# ---- lane queue: every lane advances its own node ---------------------------
+
+@pytest.mark.parametrize("block,chunk", [(64, 64), (256, 512), (128, 1024)])
+def test_lane_queue_batch_sums(lib, block, chunk):
+    """Weekly sums of an uneven batch (SIR and SISe sets, many nodes that
+    start without infection and finish at once) from the lane-queue kernel,
+    against oracle runs of every replicate; counters against the lockstep
+    kernel (draws included) and the oracle."""
+    sets = W.ensemble_sets(seed=41, n_sets=8, replicates=3, days=80, nn_range=(50, 900))
+    batch = [(st.spec, 3) for st in sets]
+    m = lib.Model(batch, record=lib.RECORD_SUMS, lane_queue=1, block=block, chunk=chunk)
+    info = m.launch_info()
+    _say("lane queue", info)
+    assert info["mode"] == 3 and info["chunk"] == chunk and info["block"] == block, info
+    m.run(19, 7)
+    assert m.wait() == 0, m.error_info()
+    sums = m.sums()
+    c = m.counters()
+    lock = lib.Model(batch, record=lib.RECORD_SUMS, lane_queue=2)
+    assert lock.launch_info()["mode"] == 0
+    lock.run(19, 7)
+    assert lock.wait() == 0
+    assert np.array_equal(sums, lock.sums())
+    assert c == lock.counters()
+    tr = nd = 0
+    for r in range(m.runs):
+        spec = sets[r // 3].spec
+        ref = oracle_run(spec, 19, 7 + r)
+        assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), r
+        tr += ref["transitions"]
+        nd += ref["node_days"]
+    assert (c["transitions"], c["node_days"]) == (tr, nd)
+
+
+@pytest.mark.parametrize("case", ["shifts", "sise_events", "birth_death"])
+def test_lane_queue_full_records(lib, case):
+    """Whole trajectories from the lane-queue kernel with node-local events
+    (internal transfers with shifts, proportional exits, two-row enters),
+    SISe with events (phi bit-identical) and linear birth-death nodes that die
+    out, bit-exact against the oracle."""
+    if case == "shifts":
+        spec = _without_transfers(W.sir_with_shifts(seed=8, Nn=700, days=50))
+    elif case == "sise_events":
+        full = W.sise_with_events(seed=12, Nn=900, days=120)
+        keep = np.asarray(full.events["event"]) != W.EXTTRANS
+        ev = {k: np.asarray(v)[keep] for k, v in full.events.items()}
+        spec = W.sise_spec(full.u0, full.tspan, 0.0175, 0.1, 1.0, (0.1, 0.12, 0.1, 0.11), events=ev,
+                           name="sise-node-events")
+    else:
+        spec = W.birth_death_spec(np.random.default_rng(5).integers(0, 40, 1500), np.arange(0, 30), 0.3, 0.4)
+    m, ref, rc = _run_both(lib, spec, 37, 11, lane_queue=1, chunk=128, block=128)
+    assert m.launch_info()["mode"] == 3
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what=f"lane queue {case}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
+@pytest.mark.parametrize("case", ["overdraw_e1", "negative_rate", "neg_state"])
+def test_lane_queue_first_error(lib, case):
+    """The first error in the serial order (day, phase, index) from the
+    lane-queue kernel equals the oracle's."""
+    u0 = np.tile([[500, 20, 0]], (300, 1))
+    beta, rows, S = 0.3, [], None
+    if case == "overdraw_e1":
+        rows = [(W.EXIT, 6, 250, 0, 400, 0.0, 1, -1), (W.EXIT, 6, 40, 0, 900, 0.0, 0, -1),
+                (W.EXIT, 9, 3, 0, 900, 0.0, 0, -1)]
+    elif case == "negative_rate":
+        beta = -0.01
+    spec = W.sir_spec(u0, np.arange(0, 12), beta, 0.1, events=W.make_events(rows))
+    if case == "neg_state":
+        spec.S = np.array([[-1, 0], [1, -1], [-1, 1]])
+    m, ref, rc = _run_both(lib, spec, 5, 0, lane_queue=1, chunk=64, block=64)
+    info = m.error_info()
+    assert rc == ref["status"] != 0
+    assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
+
+
+def test_lane_queue_graph_replays(lib):
+    """A lane-queue batch captured in a HIP graph: every replay (other work
+    between them) equals a plain run."""
+    sets = W.ensemble_sets(seed=43, n_sets=4, replicates=4, days=50, nn_range=(100, 600))
+    batch = [(st.spec, 4) for st in sets]
+    g = lib.Model(batch, record=lib.RECORD_SUMS, lane_queue=1, graph=1, chunk=256)
+    plain = lib.Model(batch, record=lib.RECORD_SUMS, lane_queue=1, chunk=256)
+    for seed in (3, 4, 3):
+        g.run(seed, 2)
+        assert g.wait() == 0
+        plain.run(seed, 2)
+        assert plain.wait() == 0
+        assert np.array_equal(g.sums(), plain.sums()), seed
