@@ -98,6 +98,11 @@ struct siminf_model {
     RunParams* h_rp = nullptr;  // pinned host staging of d_rp
     hipGraph_t graph = nullptr;  // options.graph: the captured init and SSA launches
     hipGraphExec_t gexec = nullptr;
+    // model groups after the first run on side streams, forked from and
+    // joined back into the run's stream, so that their kernels overlap
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -910,6 +915,17 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
     if (to_device(m->owned, pos, &m->d_pos)) return hip_fail(m);
     for (hipEvent_t& e : m->ev)
         if (hipEventCreate(&e) != hipSuccess) return hip_fail(m);
+    if (m->groups.size() > 1) {
+        if (hipEventCreateWithFlags(&m->fork, hipEventDisableTiming) != hipSuccess) return hip_fail(m);
+        for (size_t gi = 1; gi < m->groups.size(); ++gi) {
+            hipStream_t ss = nullptr;
+            hipEvent_t je = nullptr;
+            if (hipStreamCreateWithFlags(&ss, hipStreamNonBlocking) != hipSuccess) return hip_fail(m);
+            m->side.push_back(ss);
+            if (hipEventCreateWithFlags(&je, hipEventDisableTiming) != hipSuccess) return hip_fail(m);
+            m->joins.push_back(je);
+        }
+    }
     return SIMINF_OK;
 }
 
@@ -992,10 +1008,26 @@ int enqueue_launches(siminf_model* m, hipStream_t st, hipEvent_t mark = nullptr)
         if (launch_init(p, 0, 0, 0, true, m->d_sums_init, m->sums_len, st) != hipSuccess) return SIMINF_E_DEVICE;
     }
     if (mark && hipEventRecord(mark, st) != hipSuccess) return SIMINF_E_DEVICE;
-    for (Group& g : m->groups) {
-        if (g.n == 0) continue;
+    // the first non-empty group on the run's stream, every other one on a
+    // side stream that waits for the initialisation and is waited for
+    std::vector<size_t> busy;
+    for (size_t gi = 0; gi < m->groups.size(); ++gi)
+        if (m->groups[gi].n > 0) busy.push_back(gi);
+    if (busy.size() > 1 && hipEventRecord(m->fork, st) != hipSuccess) return SIMINF_E_DEVICE;
+    for (size_t j = 1; j < busy.size(); ++j) {
+        const Group& g = m->groups[busy[j]];
+        hipStream_t ss = m->side[j - 1];
+        if (hipStreamWaitEvent(ss, m->fork, 0) != hipSuccess ||
+            launch_group(g.model, g.p, g.block, g.blocks, g.shmem, ss) != hipSuccess ||
+            hipEventRecord(m->joins[j - 1], ss) != hipSuccess)
+            return SIMINF_E_DEVICE;
+    }
+    if (!busy.empty()) {
+        const Group& g = m->groups[busy[0]];
         if (launch_group(g.model, g.p, g.block, g.blocks, g.shmem, st) != hipSuccess) return SIMINF_E_DEVICE;
     }
+    for (size_t j = 1; j < busy.size(); ++j)
+        if (hipStreamWaitEvent(st, m->joins[j - 1], 0) != hipSuccess) return SIMINF_E_DEVICE;
     return SIMINF_OK;
 }
 
@@ -1335,6 +1367,11 @@ void siminf_destroy(siminf_model* m) {
     for (hipEvent_t e : m->ev)
         if (e) (void)hipEventDestroy(e);
     drop_graph(m);
+    for (hipEvent_t e : m->joins)
+        if (e) (void)hipEventDestroy(e);
+    if (m->fork) (void)hipEventDestroy(m->fork);
+    for (hipStream_t ss : m->side)
+        if (ss) (void)hipStreamDestroy(ss);
     if (m->h_rp) (void)hipHostFree(m->h_rp);
     if (m->stage) (void)hipFree(m->stage);
     for (void* p : m->owned) (void)hipFree(p);
