@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--lane-queue", type=int, default=0,
                     help="runs without transfers: 1 every lane advances its own node, 2 lanes in lockstep, 0 auto")
     ap.add_argument("--chunk", type=int, default=0, help="lane queue: nodes per chunk (0 auto)")
+    ap.add_argument("--batch", type=int, default=0, help="lane queue: lanes per day-end batch (0 auto)")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the run from a captured HIP graph: 1 on, 0 off, -1 on for batches without transfers")
     ap.add_argument("--no-cpu", action="store_true")
@@ -304,7 +305,7 @@ def main():
     model = siminf.Model(spec, record=siminf.RECORD_SUMS if batch else siminf.RECORD_FULL, block=args.block,
                          order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline,
                          pack=args.pack, graph=graph, group=args.group, lane_queue=args.lane_queue,
-                         chunk=args.chunk)
+                         chunk=args.chunk, batch=args.batch)
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
@@ -369,7 +370,7 @@ def main():
         "data": "synthetic",
         "config": dict(desc, seed=seed0, block=info["block"], blocks=info["blocks"],
                        kernel=["free-running", "grid-barrier", "dataflow", "lane-queue"][info["mode"]],
-                       chunk=info["chunk"],
+                       chunk=info["chunk"], batch=info["batch"],
                        wide_nodes=info["wide"], pipeline=info["pipeline"], pack=info["pack"],
                        group_nodes=info["group"], graph=graph),
         "transitions_per_s": transitions / wall,

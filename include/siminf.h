@@ -186,6 +186,9 @@ typedef struct {
                           (auto: off).  The results do not depend on it. */
     int32_t chunk;     /* lane queue: nodes per chunk (consecutive nodes of one
                           run handed to one wavefront), 64..1048576; 0 = 512 */
+    int32_t batch;     /* lane queue: lanes of a wavefront that wait at the end
+                          of a day (or without a node) before the wavefront
+                          serves them together, 1..64; 0 = 16 */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;
@@ -288,8 +291,9 @@ int siminf_error_message(const siminf_model *m, char *buf, size_t cap);
  * out[4] order, out[5] nodes carried by a whole wavefront, out[6] nodes per
  * wavefront of the one-lane-per-node ones (the pack option), out[7] nodes
  * on a group of lanes (the group option), out[8] lane queue: nodes per
- * chunk (0 = not the lane queue), out[9] dynamic LDS bytes per workgroup. */
-int siminf_launch_info(const siminf_model *m, int32_t out[10]);
+ * chunk (0 = not the lane queue), out[9] dynamic LDS bytes per workgroup,
+ * out[10] lane queue: the batch option in use, out[11] model groups. */
+int siminf_launch_info(const siminf_model *m, int32_t out[12]);
 
 /* Autotuner: runs the model `repeats` times for each candidate launch shape
  * (threads per block 64/128/256; no wavefront-wide nodes, or those whose

@@ -76,8 +76,15 @@ struct ModelSISe {
     }
     __device__ static __forceinline__ bool pts(double* v, const int32_t* u, const double* ld,
                                                const double* gd, int64_t day) {
-        int64_t r = (day - 1) % 365;
-        if (r < 0) r += 365;
+        // (day - 1) mod 365 in [0, 365); 32-bit arithmetic for the usual days
+        const int64_t dm = day - 1;
+        int64_t r;
+        if (dm >= 0 && dm <= 0x7FFFFFFF) {
+            r = (int64_t)((uint32_t)dm % 365u);
+        } else {
+            r = dm % 365;
+            if (r < 0) r += 365;
+        }
         const double doy = (double)(r + 1);
         // selects on values (not on array elements) keep the node in registers
         const double decay = pick(doy <= ld[0], gd[3],

@@ -419,8 +419,9 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
-    if (m->opt.lane_queue < 0 || m->opt.lane_queue > 2 || (m->opt.chunk != 0 && (m->opt.chunk < 64 ||
-                                                                               m->opt.chunk > (1 << 20)))) {
+    if (m->opt.lane_queue < 0 || m->opt.lane_queue > 2 ||
+        (m->opt.chunk != 0 && (m->opt.chunk < 64 || m->opt.chunk > (1 << 20))) || m->opt.batch < 0 ||
+        m->opt.batch > WAVE) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -906,7 +907,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         }
         const int nb = default_wide(m, g);
         const int rc = configure(m, g, m->opt.block, nb, m->opt.pipeline, m->opt.mode, m->opt.pack,
-                                 m->opt.group < 0 ? g.n : m->opt.group, lq);
+                                 m->opt.group < 0 ? g.n : m->opt.group, lq, m->opt.batch ? m->opt.batch : 16);
         if (rc) {
             set_create_error(m, rc, -1, -1);
             return rc;
@@ -1214,9 +1215,9 @@ int siminf_error_message(const siminf_model* m, char* buf, size_t cap) {
     return n < 0 ? SIMINF_E_ARG : SIMINF_OK;
 }
 
-int siminf_launch_info(const siminf_model* m, int32_t out[10]) {
+int siminf_launch_info(const siminf_model* m, int32_t out[12]) {
     if (!m || !out) return SIMINF_E_ARG;
-    for (int i = 0; i < 10; ++i) out[i] = 0;
+    for (int i = 0; i < 12; ++i) out[i] = 0;
     if (m->groups.empty()) return SIMINF_OK;
     const Group& g = m->groups[0];
     out[0] = g.block;
@@ -1229,6 +1230,8 @@ int siminf_launch_info(const siminf_model* m, int32_t out[10]) {
     out[7] = g.p.ngrp;
     out[8] = g.lq_chunk;
     out[9] = (int32_t)g.shmem;
+    out[10] = g.lq_chunk ? g.lq_batch : 0;
+    out[11] = (int32_t)m->groups.size();
     return SIMINF_OK;
 }
 
@@ -1278,8 +1281,9 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     const bool shaped = m->opt.lanes != 0 || m->opt.wide != 0 || m->opt.group != 0 || m->opt.pack != 0;
     if (free_only && m->opt.lane_queue != 2 && (m->opt.lane_queue == 1 || !shaped)) {
         const int ch = m->opt.chunk > 0 ? m->opt.chunk : 512;
+        const std::vector<int> batches = m->opt.batch > 0 ? std::vector<int>{m->opt.batch} : std::vector<int>{4, 8, 16};
         for (int block : {64, 128, 256})
-            for (int lqb : {4, 8, 16}) cands.push_back({block, 0, 2, WAVE, -1, ch, lqb});
+            for (int lqb : batches) cands.push_back({block, 0, 2, WAVE, -1, ch, lqb});
     }
     if (cands.empty()) return SIMINF_E_UNSUPPORTED;
     double best = 1e300;

@@ -898,6 +898,7 @@ struct LaneState {
     bool open = false;  // inside a day with lambda > 0: the next draw is due
     uint32_t node = 0, tag = 0, step = 0;
     uint32_t dd = 0, dt = 0;  // draws and transitions of the current day
+    int fail = 0;             // an error of the current day's SSA (code), taken up at its end
     double t = 0.0, T = 0.0, w0 = 0.0, w1 = 0.0, lam = 0.0;
 };
 
@@ -945,6 +946,7 @@ __device__ __forceinline__ void lane_open_day(const KParams& p, LaneState<M>& L,
     L.T = (double)(p.T1 + L.b);
     L.t = L.b == 0 ? p.t0 : L.T - 1.0;
     L.step = 0;
+    L.fail = 0;
     L.dd = 0;
     L.dt = 0;
     L.w0 = M::template rate<0>(L.u, L.v, L.ld, gd);
@@ -1095,39 +1097,30 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
         // (or no lane has a draw due); those are then served together
         for (;;) {
             if (L.open) {
-                if (L.step == STEP_LIMIT) {
-                    lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], E_STEP_LIMIT, tally);
-                } else {
-                    L.dd += 1;
-                    const StepRandoms r =
-                        step_randoms(k0, k1, L.step, (uint32_t)(int32_t)(p.T1 + L.b), L.node, L.tag);
-                    const double tau = r.e / L.lam;
-                    const double tn = L.t + tau;
-                    const Transition<M> nx =
-                        transition_of<M>(p, L.u, L.v, L.ld, gdl + L.slot * M::NGD, L.w0, L.w1, L.lam * r.r2);
-                    if (tn >= L.T) {
-                        L.open = false;
-                    } else {
-                        L.t = tn;
+                // the step limit, the draw, the day boundary and the
+                // transition as selects (one branch for the whole step); an
+                // error is taken up with the lane's day end
+                const bool lim = L.step == STEP_LIMIT;
+                const StepRandoms r = step_randoms(k0, k1, L.step, (uint32_t)(int32_t)(p.T1 + L.b), L.node, L.tag);
+                const double tau = r.e / L.lam;
+                const double tn = L.t + tau;
+                const Transition<M> nx =
+                    transition_of<M>(p, L.u, L.v, L.ld, gdl + L.slot * M::NGD, L.w0, L.w1, L.lam * r.r2);
+                const bool go = !lim && !(tn >= L.T);
+                L.dd += lim ? 0u : 1u;
+                L.dt += go ? 1u : 0u;
+                L.t = go ? tn : L.t;
 #pragma unroll
-                        for (int c = 0; c < M::NC; ++c) L.u[c] = nx.u[c];
-                        L.w0 = nx.w0;
-                        L.w1 = nx.w1;
-                        L.dt += 1;
-                        if (nx.err) {
-                            lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], nx.err, tally);
-                        } else {
-                            double lam = 0.0;
-                            lam = lam + L.w0;
-                            lam = lam + L.w1;
-                            L.lam = lam;
-                            if (!(lam > 0.0))
-                                L.open = false;
-                            else
-                                ++L.step;
-                        }
-                    }
-                }
+                for (int c = 0; c < M::NC; ++c) L.u[c] = go ? nx.u[c] : L.u[c];
+                L.w0 = go ? nx.w0 : L.w0;
+                L.w1 = go ? nx.w1 : L.w1;
+                double lam = 0.0;
+                lam = lam + L.w0;
+                lam = lam + L.w1;
+                L.lam = lam;
+                L.fail = lim ? E_STEP_LIMIT : go ? nx.err : 0;
+                L.open = go && nx.err == 0 && lam > 0.0;
+                L.step += L.open ? 1u : 0u;
             }
             const unsigned long long idle = __ballot(!L.open);
             if (__popcll(idle) >= (unsigned)p.lq_batch || idle == ~0ull) break;
@@ -1140,8 +1133,9 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
             atomicAdd(tally + LQ_TR, (unsigned long long)L.dt);
             L.dd = 0;
             L.dt = 0;
-            bool dead = false;
-            while (L.cur < L.cend && (double)L.etime <= L.T) {
+            bool dead = L.fail != 0;
+            if (dead) lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], L.fail, tally);
+            while (!dead && L.cur < L.cend && (double)L.etime <= L.T) {
                 const int rc = apply_event<M::NC>(p.e1.rec[L.cur], p.e1.prop, L.cur, seed, L.tag, L.u, L.u);
                 if (rc) {
                     lane_fail<M>(p, L, PH_E1, p.e1.ordinal[L.cur], rc, tally);

@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
                 ("pipeline", ctypes.c_int32), ("mode", ctypes.c_int32), ("wide", ctypes.c_int32),
                 ("lattice", ctypes.c_int32), ("wait_ms", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("pack", ctypes.c_int32), ("group", ctypes.c_int32), ("lane_queue", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
 # exported entry points: name -> (restype, argtypes)
@@ -190,12 +190,12 @@ class Model:
     def __init__(self, spec, record: int = RECORD_FULL, block: int = 0, order: int = 0,
                  lanes: int = 0, max_blocks: int = 0, pipeline: int = 0, mode: int = 0, wide: int = 0,
                  lattice: int = 0, wait_ms: int = 0, graph: int = 0, pack: int = 0, group: int = 0,
-                 lane_queue: int = 0, chunk: int = 0):
+                 lane_queue: int = 0, chunk: int = 0, batch: int = 0):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p()
         opt = Options(record, block, order, lanes, max_blocks, pipeline, mode, wide, lattice, wait_ms, graph, pack,
-                      group, lane_queue, chunk)
+                      group, lane_queue, chunk, batch)
         keep: list = []
         if isinstance(spec, (list, tuple)):
             specs = [s for s, _ in spec]
@@ -282,11 +282,11 @@ class Model:
         return dict(kernel_ms=float(out[0]), run_ms=float(out[1]))
 
     def launch_info(self) -> dict:
-        out = np.zeros(10, dtype=np.int32)
+        out = np.zeros(12, dtype=np.int32)
         self._lib.siminf_launch_info(self._h, _ptr(out))
         return dict(block=int(out[0]), blocks=int(out[1]), mode=int(out[2]), pipeline=int(out[3]),
                     order=int(out[4]), wide=int(out[5]), pack=int(out[6]), group=int(out[7]),
-                    chunk=int(out[8]), lds=int(out[9]))
+                    chunk=int(out[8]), lds=int(out[9]), batch=int(out[10]), groups=int(out[11]))
 
     def autotune(self, seed: int = 1, repeats: int = 2, hip_stream=None) -> float:
         """Pick the fastest launch shape (see siminf_autotune); returns its ms."""
