@@ -262,7 +262,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         const int wpb = block / WAVE;
         const size_t lds = lane_queue_lds(m, g, wpb);
         if (lds > (size_t)LQ_LDS_BYTES) return SIMINF_E_UNSUPPORTED;
-        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, 0, false, block, lds, true);
+        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, pipeline == 1 ? 1 : 0, false, block, lds, true);
         if (per_cu <= 0) return SIMINF_E_DEVICE;
         // chunks: consecutive nodes of one run, at most lq_chunk of them and,
         // past a wavefront's worth of nodes, at most 1/8 of one wavefront's
@@ -302,7 +302,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         p.lane_queue = 1;
         p.nlchunks = (int)ch.size();
         p.lchunks = g.d_chunks;
-        p.pipeline = 0;
+        p.pipeline = pipeline == 1 ? 1 : 0;
         p.nbig = 0;
         p.pack = WAVE;
         p.ngrp = 0;
@@ -1283,7 +1283,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
         const int ch = m->opt.chunk > 0 ? m->opt.chunk : 512;
         const std::vector<int> batches = m->opt.batch > 0 ? std::vector<int>{m->opt.batch} : std::vector<int>{4, 8, 16};
         for (int block : {64, 128, 256})
-            for (int lqb : batches) cands.push_back({block, 0, 2, WAVE, -1, ch, lqb});
+            for (int lqb : batches)
+                for (int pipe : {2, 1}) cands.push_back({block, 0, pipe, WAVE, -1, ch, lqb});
     }
     if (cands.empty()) return SIMINF_E_UNSUPPORTED;
     double best = 1e300;

@@ -899,6 +899,7 @@ struct LaneState {
     uint32_t node = 0, tag = 0, step = 0;
     uint32_t dd = 0, dt = 0;  // draws and transitions of the current day
     int fail = 0;             // an error of the current day's SSA (code), taken up at its end
+    double e = 0.0, r2 = 0.0; // with pipelining: the random numbers of the next draw
     double t = 0.0, T = 0.0, w0 = 0.0, w1 = 0.0, lam = 0.0;
 };
 
@@ -940,7 +941,7 @@ __device__ __forceinline__ void lane_fail(const KParams& p, LaneState<M>& L, int
 // new unit of time), lambda, and whether a draw is due.  A node whose rates
 // are all zero with no event left and a fixed point of the post-time step
 // is finished here, its state recorded for the rest of the run.
-template <class M>
+template <class M, bool PIPE>
 __device__ __forceinline__ void lane_open_day(const KParams& p, LaneState<M>& L, unsigned long long* slotbase,
                                               const double* gd, const int* rec_off, unsigned long long* tally) {
     L.T = (double)(p.T1 + L.b);
@@ -960,6 +961,12 @@ __device__ __forceinline__ void lane_open_day(const KParams& p, LaneState<M>& L,
     lam = lam + L.w1;
     L.lam = lam;
     L.open = lam > 0.0;
+    if (PIPE && L.open) {
+        const StepRandoms r = step_randoms((uint32_t)p.rp->seed, (uint32_t)(p.rp->seed >> 32), 0u,
+                                           (uint32_t)(int32_t)(p.T1 + L.b), L.node, L.tag);
+        L.e = r.e;
+        L.r2 = r.r2;
+    }
     if (!L.open && L.cur >= L.cend && M::pts_fixed(L.v, L.u)) {
         lane_record<M>(p, L, slotbase, rec_off[L.b], p.ntspan);
         atomicAdd(tally + LQ_ND, (unsigned long long)(p.nb - L.b));
@@ -987,7 +994,7 @@ __device__ __forceinline__ void lane_load(const KParams& p, LaneState<M>& L, int
     L.b = 0;
 }
 
-template <class M>
+template <class M, bool PIPE>
 __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
     extern __shared__ unsigned long long lq_lds[];
     const KParams& p = pa;
@@ -1082,7 +1089,7 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
                 const bool me = ((freem >> lane) & 1ull) && rank < take;
                 if (me) {
                     lane_load<M>(p, L, next + rank, cslot, cslot == 0 ? srun0 : srun1, stream_base);
-                    lane_open_day<M>(p, L, mine + L.slot * per_slot, gdl + L.slot * M::NGD, rec_off, tally);
+                    lane_open_day<M, PIPE>(p, L, mine + L.slot * per_slot, gdl + L.slot * M::NGD, rec_off, tally);
                 }
                 next += take;
                 freem &= ~__ballot(me);
@@ -1101,7 +1108,17 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
                 // transition as selects (one branch for the whole step); an
                 // error is taken up with the lane's day end
                 const bool lim = L.step == STEP_LIMIT;
-                const StepRandoms r = step_randoms(k0, k1, L.step, (uint32_t)(int32_t)(p.T1 + L.b), L.node, L.tag);
+                const uint32_t dw = (uint32_t)(int32_t)(p.T1 + L.b);
+                // with PIPE the step's numbers were computed by the previous
+                // step, which computes the next step's (kept only if the day
+                // goes on) beside its own dependent chain
+                StepRandoms r, rn{0.0, 0.0};
+                if constexpr (PIPE) {
+                    r = {L.e, L.r2};
+                    rn = step_randoms(k0, k1, L.step + 1u, dw, L.node, L.tag);
+                } else {
+                    r = step_randoms(k0, k1, L.step, dw, L.node, L.tag);
+                }
                 const double tau = r.e / L.lam;
                 const double tn = L.t + tau;
                 const Transition<M> nx =
@@ -1121,6 +1138,10 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
                 L.fail = lim ? E_STEP_LIMIT : go ? nx.err : 0;
                 L.open = go && nx.err == 0 && lam > 0.0;
                 L.step += L.open ? 1u : 0u;
+                if constexpr (PIPE) {
+                    L.e = rn.e;
+                    L.r2 = rn.r2;
+                }
             }
             const unsigned long long idle = __ballot(!L.open);
             if (__popcll(idle) >= (unsigned)p.lq_batch || idle == ~0ull) break;
@@ -1157,7 +1178,7 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
                 if (L.b >= p.nb)
                     L.k = -1;
                 else
-                    lane_open_day<M>(p, L, slotbase, gd, rec_off, tally);
+                    lane_open_day<M, PIPE>(p, L, slotbase, gd, rec_off, tally);
             }
         }
     }
@@ -1571,7 +1592,7 @@ const void* kernel_for(int mode, bool grp) {
 
 template <class M>
 const void* kernel_for(int mode, int pipeline, bool grp, bool lq) {
-    if (mode == MODE_FREE && lq) return (const void*)lane_kernel<M>;
+    if (mode == MODE_FREE && lq) return pipeline ? (const void*)lane_kernel<M, true> : (const void*)lane_kernel<M, false>;
     return pipeline ? kernel_for<M, true>(mode, grp) : kernel_for<M, false>(mode, grp);
 }
 

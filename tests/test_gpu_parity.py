@@ -506,18 +506,21 @@ def test_internal_transfers_free_running(lib, opts):
 
 # ---- lane queue: every lane advances its own node ---------------------------
 
-@pytest.mark.parametrize("block,chunk", [(64, 64), (256, 512), (128, 1024)])
-def test_lane_queue_batch_sums(lib, block, chunk):
+@pytest.mark.parametrize("block,chunk,lqb,pipeline", [(64, 64, 1, 2), (256, 512, 16, 1), (128, 1024, 64, 2),
+                                                      (128, 256, 8, 1)])
+def test_lane_queue_batch_sums(lib, block, chunk, lqb, pipeline):
     """Weekly sums of an uneven batch (SIR and SISe sets, many nodes that
     start without infection and finish at once) from the lane-queue kernel,
     against oracle runs of every replicate; counters against the lockstep
     kernel (draws included) and the oracle."""
     sets = W.ensemble_sets(seed=41, n_sets=8, replicates=3, days=80, nn_range=(50, 900))
     batch = [(st.spec, 3) for st in sets]
-    m = lib.Model(batch, record=lib.RECORD_SUMS, lane_queue=1, block=block, chunk=chunk)
+    m = lib.Model(batch, record=lib.RECORD_SUMS, lane_queue=1, block=block, chunk=chunk, batch=lqb,
+                  pipeline=pipeline)
     info = m.launch_info()
     _say("lane queue", info)
     assert info["mode"] == 3 and info["chunk"] == chunk and info["block"] == block, info
+    assert info["batch"] == lqb and info["pipeline"] == (1 if pipeline == 1 else 0), info
     m.run(19, 7)
     assert m.wait() == 0, m.error_info()
     sums = m.sums()
@@ -538,8 +541,9 @@ def test_lane_queue_batch_sums(lib, block, chunk):
     assert (c["transitions"], c["node_days"]) == (tr, nd)
 
 
+@pytest.mark.parametrize("pipeline", [1, 2])
 @pytest.mark.parametrize("case", ["shifts", "sise_events", "birth_death"])
-def test_lane_queue_full_records(lib, case):
+def test_lane_queue_full_records(lib, case, pipeline):
     """Whole trajectories from the lane-queue kernel with node-local events
     (internal transfers with shifts, proportional exits, two-row enters),
     SISe with events (phi bit-identical) and linear birth-death nodes that die
@@ -554,7 +558,7 @@ def test_lane_queue_full_records(lib, case):
                            name="sise-node-events")
     else:
         spec = W.birth_death_spec(np.random.default_rng(5).integers(0, 40, 1500), np.arange(0, 30), 0.3, 0.4)
-    m, ref, rc = _run_both(lib, spec, 37, 11, lane_queue=1, chunk=128, block=128)
+    m, ref, rc = _run_both(lib, spec, 37, 11, lane_queue=1, chunk=128, block=128, pipeline=pipeline)
     assert m.launch_info()["mode"] == 3
     assert rc == 0 and ref["status"] == 0
     _compare(m, ref, what=f"lane queue {case}")
@@ -562,8 +566,9 @@ def test_lane_queue_full_records(lib, case):
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
 
 
-@pytest.mark.parametrize("case", ["overdraw_e1", "negative_rate", "neg_state"])
-def test_lane_queue_first_error(lib, case):
+@pytest.mark.parametrize("pipeline", [1, 2])
+@pytest.mark.parametrize("case", ["overdraw_e1", "negative_rate", "neg_state", "step_limit"])
+def test_lane_queue_first_error(lib, case, pipeline):
     """The first error in the serial order (day, phase, index) from the
     lane-queue kernel equals the oracle's."""
     u0 = np.tile([[500, 20, 0]], (300, 1))
@@ -576,7 +581,12 @@ def test_lane_queue_first_error(lib, case):
     spec = W.sir_spec(u0, np.arange(0, 12), beta, 0.1, events=W.make_events(rows))
     if case == "neg_state":
         spec.S = np.array([[-1, 0], [1, -1], [-1, 1]])
-    m, ref, rc = _run_both(lib, spec, 5, 0, lane_queue=1, chunk=64, block=64)
+    if case == "step_limit":
+        # immigration at 3e7 per day: both nodes reach the 2^24-draw limit on day 0
+        x0 = np.zeros(2, dtype=np.int64)
+        spec = W.birth_death_spec(x0, np.arange(0, 3), 1.0, 0.5, immigration=True)
+        spec.gdata = np.array([3.0e7, 0.0])
+    m, ref, rc = _run_both(lib, spec, 5, 0, lane_queue=1, chunk=64, block=64, pipeline=pipeline)
     info = m.error_info()
     assert rc == ref["status"] != 0
     assert (info["code"], info["step"], info["phase"], info["index"]) == ref["error"]
