@@ -386,6 +386,24 @@ int siminf_mlp_adamw(siminf_mlp *m, float lr, float beta1, float beta2, float ep
 /* Frees the network (waits for the device). */
 void siminf_mlp_destroy(siminf_mlp *m);
 
+/* The surrogate's answer from an ensemble of `members` networks of the same
+ * input and output widths (the learned part of the build, not in the
+ * paper): each member maps X[B][dims[0]] (device, float32, standardised
+ * inputs) to standardised outputs p; per output j, y = p * y_std[j] +
+ * y_mean[j] (device float32 vectors of the output width), then
+ *   Y[b][j]          = mean of y over the members (device float32 [B][N]),
+ *   disagreement[b]  = mean over j of the members' sample standard deviation
+ *                      of y (divisor members - 1; 0 for one member),
+ * computed in binary64 and rounded once to float32.  Enqueued on hip_stream;
+ * a device workspace of members x B x N floats is taken from the stream's
+ * memory pool for the call.  1 <= members <= 64, B >= 1 (any size: members
+ * run in slices of their largest batch); SIMINF_E_ARG for mismatched widths
+ * or null pointers.  Uses each member's activation buffers: no other work
+ * on those networks may overlap the call. */
+int siminf_mlp_ensemble_predict(siminf_mlp *const *nets, int32_t members, const float *X, int32_t B,
+                                const float *y_mean, const float *y_std, float *Y, float *disagreement,
+                                void *hip_stream);
+
 /* C[M][N] (float32, row stride ldc) = A B with bfloat16 operands (uint16_t
  * bit patterns): A is M x K, stored A[m*lda + k] (a_trans = 0) or
  * A[k*lda + m] (a_trans = 1); B is K x N, stored B[n*ldb + k] (b_trans = 0)

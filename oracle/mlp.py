@@ -117,3 +117,20 @@ def adamw_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, weigh
 def init_state(params):
     return {"t": 0, "m": [np.zeros_like(a) for W, b in params for a in (W, b)],
             "v": [np.zeros_like(a) for W, b in params for a in (W, b)]}
+
+
+def ensemble_combine(P, y_mean, y_std):
+    """The ensemble's answer from its members' standardised outputs P
+    (members, B, N): y = P * y_std + y_mean per member, the mean over the
+    members (B, N) and the disagreement (B,) = mean over the outputs of the
+    members' sample standard deviation (divisor members - 1; 0 for one
+    member).  Float64, written out from the definition."""
+    P = np.asarray(P, dtype=np.float64)
+    K = P.shape[0]
+    y = P * np.asarray(y_std, dtype=np.float64)[None, None, :] + np.asarray(y_mean, dtype=np.float64)[None, None, :]
+    mean = y.sum(axis=0) / K
+    if K > 1:
+        sd = np.sqrt(((y - mean[None]) ** 2).sum(axis=0) / (K - 1))
+    else:
+        sd = np.zeros_like(mean)
+    return mean, sd.mean(axis=1)

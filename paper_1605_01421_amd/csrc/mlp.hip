@@ -354,6 +354,39 @@ __global__ void adamw_kernel(float* p, const float* g, float* m, float* v, uint1
     }
 }
 
+// The ensemble's answer for sample b (one workgroup per sample): every
+// member's standardised output p is mapped back, y = p * y_std + y_mean
+// (binary64), Y = the members' mean, and the disagreement is the mean over
+// the outputs of the members' sample standard deviation (divisor K - 1; 0
+// for a single member).  The sums run in a fixed order.
+__global__ void __launch_bounds__(256) ensemble_combine_kernel(const float* P, int K, int B, int N,
+                                                               const float* ymean, const float* ystd, float* Y,
+                                                               float* dis) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double ssum = 0.0;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const double sd = ystd[j], mu = ymean[j];
+        double mean = 0.0;
+        for (int k = 0; k < K; ++k) mean += (double)P[((size_t)k * B + b) * N + j] * sd + mu;
+        mean /= (double)K;
+        double m2 = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double d = ((double)P[((size_t)k * B + b) * N + j] * sd + mu) - mean;
+            m2 += d * d;
+        }
+        Y[(size_t)b * N + j] = (float)mean;
+        ssum += K > 1 ? sqrt(m2 / (double)(K - 1)) : 0.0;
+    }
+    red[threadIdx.x] = ssum;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dis[b] = (float)(red[0] / (double)N);
+}
+
 int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
 
 }  // namespace
@@ -407,6 +440,37 @@ int mlp_forward(siminf_mlp* m, const float* X, int B, hipStream_t st, bool train
             e = gemm<false, false, EPI_STORE>(g, st);
         }
         if (e != hipSuccess) return SIMINF_E_DEVICE;
+    }
+    return SIMINF_OK;
+}
+// The ensemble prediction into the workspace `work` (members x B x N
+// floats): each member's forward pass in slices of its largest batch, its
+// outputs copied into its part of the workspace, then the combination.
+int ensemble_predict(siminf_mlp* const* nets, int K, const float* X, int B, const float* ymean, const float* ystd,
+                     float* Y, float* dis, hipStream_t st, float* work) {
+    const int din = nets[0]->dims[0], N = nets[0]->dims[nets[0]->L];
+    for (int k = 0; k < K; ++k) {
+        siminf_mlp* m = nets[k];
+        for (int b0 = 0; b0 < B; b0 += m->max_batch) {
+            const int bs = std::min(m->max_batch, B - b0);
+            const int rc = mlp_forward(m, X + (size_t)b0 * din, bs, st, false);
+            if (rc) return rc;
+            if (hipMemcpyAsync(work + ((size_t)k * B + b0) * N, m->Z[m->L - 1], sizeof(float) * (size_t)bs * N,
+                               hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return SIMINF_E_DEVICE;
+        }
+    }
+    ensemble_combine_kernel<<<B, 256, 0, st>>>(work, K, B, N, ymean, ystd, Y, dis);
+    return hipGetLastError() == hipSuccess ? SIMINF_OK : SIMINF_E_DEVICE;
+}
+
+int ensemble_check(siminf_mlp* const* nets, int K, const float* X, int B, const float* ymean, const float* ystd,
+                   const float* Y, const float* dis) {
+    if (!nets || K < 1 || K > 64 || !X || B < 1 || !ymean || !ystd || !Y || !dis) return SIMINF_E_ARG;
+    for (int k = 0; k < K; ++k) {
+        if (!nets[k]) return SIMINF_E_ARG;
+        if (nets[k]->dims[0] != nets[0]->dims[0] || nets[k]->dims[nets[k]->L] != nets[0]->dims[nets[0]->L])
+            return SIMINF_E_ARG;
     }
     return SIMINF_OK;
 }
@@ -581,6 +645,20 @@ void siminf_mlp_destroy(siminf_mlp* m) {
     (void)hipDeviceSynchronize();
     for (void* p : m->owned) (void)hipFree(p);
     delete m;
+}
+
+int siminf_mlp_ensemble_predict(siminf_mlp* const* nets, int32_t members, const float* X, int32_t B,
+                                const float* y_mean, const float* y_std, float* Y, float* disagreement,
+                                void* hip_stream) {
+    int rc = ensemble_check(nets, members, X, B, y_mean, y_std, Y, disagreement);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t n = (size_t)members * B * nets[0]->dims[nets[0]->L];
+    float* work = nullptr;
+    if (hipMallocAsync((void**)&work, sizeof(float) * n, st) != hipSuccess) return SIMINF_E_ALLOC;
+    rc = ensemble_predict(nets, members, X, B, y_mean, y_std, Y, disagreement, st, work);
+    if (hipFreeAsync(work, st) != hipSuccess && rc == SIMINF_OK) rc = SIMINF_E_DEVICE;
+    return rc;
 }
 
 int siminf_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t a_trans,

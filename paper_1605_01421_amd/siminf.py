@@ -85,6 +85,7 @@ SIGNATURES = {
     "siminf_mlp_adamw": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, _P]),
     "siminf_mlp_destroy": (None, [_P]),
+    "siminf_mlp_ensemble_predict": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "siminf_gemm_bf16": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                         ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                         _P]),
@@ -438,6 +439,25 @@ class MLP:
         rc = self._lib.siminf_mlp_adamw(self._h, lr, beta1, beta2, eps, weight_decay, _stream_handle(hip_stream))
         if rc != SIMINF_OK:
             raise SiminfError(rc, "siminf_mlp_adamw")
+
+
+def ensemble_predict(nets, X, y_mean, y_std, hip_stream=None):
+    """siminf_mlp_ensemble_predict: mean prediction (B, N) and disagreement
+    (B,) of the networks `nets` (MLP objects) on X (B, dims[0]); y_mean,
+    y_std are float32 CUDA tensors of the output width.  Torch tensors."""
+    import torch
+    B, N = X.shape[0], nets[0].dims[-1]
+    Y = torch.empty((B, N), dtype=torch.float32, device=X.device)
+    dis = torch.empty((B,), dtype=torch.float32, device=X.device)
+    arr = (ctypes.c_void_p * len(nets))(*[n._h.value for n in nets])
+    rc = load().siminf_mlp_ensemble_predict(ctypes.cast(arr, ctypes.c_void_p), len(nets),
+                                            ctypes.c_void_p(X.data_ptr()), B,
+                                            ctypes.c_void_p(y_mean.data_ptr()), ctypes.c_void_p(y_std.data_ptr()),
+                                            ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(dis.data_ptr()),
+                                            _stream_handle(hip_stream))
+    if rc != SIMINF_OK:
+        raise SiminfError(rc, "siminf_mlp_ensemble_predict")
+    return Y, dis
 
 
 def gemm_bf16(A_bits, B_bits, M, N, K, lda, a_trans, ldb, b_trans, C, ldc, hip_stream=None):

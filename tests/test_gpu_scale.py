@@ -56,13 +56,33 @@ def test_sise_events_full_size(lib):
 
 @pytest.fixture(scope="module")
 def batch(lib):
+    """The batch as the benchmark runs it: autotuned launch shape, replayed
+    from a captured HIP graph."""
     sets = W.ensemble_sets(seed=3, n_sets=64, replicates=64)
-    m = lib.Model([(s.spec, 64) for s in sets], record=lib.RECORD_SUMS)
+    m = lib.Model([(s.spec, 64) for s in sets], record=lib.RECORD_SUMS, graph=1)
     _say("batch", m.runs, "runs", sum(s.spec.Nn for s in sets) * 64, "nodes")
+    best = m.autotune(seed=7, repeats=1)
+    _say("autotuned", m.launch_info(), f"{best:.1f} ms")
     m.run(79, 0)
     assert m.wait() == 0, m.error_info()
     _say("batch done", m.launch_info(), m.timing())
     return sets, m, m.sums()
+
+
+def test_batch_full_size_shapes_agree(lib, batch):
+    """The autotuned, graph-replayed batch equals plain launches of the
+    lockstep kernel and of the lane-queue kernel, sum for sum and counter for
+    counter."""
+    sets, m, sums = batch
+    c = m.counters()
+    for lq in (2, 1):
+        other = lib.Model([(s.spec, 64) for s in sets], record=lib.RECORD_SUMS, lane_queue=lq)
+        other.run(79, 0)
+        assert other.wait() == 0
+        _say("plain", other.launch_info(), other.timing())
+        assert np.array_equal(other.sums(), sums), lq
+        assert other.counters() == c, lq
+        other.close()
 
 
 @pytest.mark.parametrize("run", [0, 1, 2047, 2048, 4095])

@@ -121,3 +121,26 @@ def test_bf16_rounding_matches_torch():
     want = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(mlp.bf16(x), want)
     assert mlp.bf16(np.array([1 + 2 ** -8]))[0] == 1.0  # tie to even
+
+
+def test_ensemble_combine_closed_forms():
+    """Members whose outputs form an arithmetic progression c + d k
+    (k = 0..K-1) have mean c + d (K-1)/2 and sample standard deviation
+    |d| sqrt(K (K+1) / 12); the de-standardisation scales both by y_std and
+    shifts the mean by y_mean; one member disagrees by exactly 0, identical
+    members by no more than the rounding of their mean."""
+    rng = np.random.default_rng(9)
+    B, N = 5, 7
+    c = rng.normal(size=(B, N))
+    d = rng.normal(size=(B, N))
+    ymu, ysd = rng.normal(size=N), rng.uniform(0.5, 2.0, size=N)
+    for K in (2, 3, 4, 7):
+        P = np.stack([c + d * k for k in range(K)])
+        mean, dis = mlp.ensemble_combine(P, ymu, ysd)
+        assert np.allclose(mean, (c + d * (K - 1) / 2) * ysd + ymu, rtol=1e-13, atol=1e-13)
+        want = (np.abs(d) * ysd * math.sqrt(K * (K + 1) / 12.0)).mean(axis=1)
+        assert np.allclose(dis, want, rtol=1e-12)
+    mean, dis = mlp.ensemble_combine(c[None], ymu, ysd)
+    assert np.allclose(mean, c * ysd + ymu) and np.all(dis == 0.0)
+    mean, dis = mlp.ensemble_combine(np.stack([c, c, c]), ymu, ysd)
+    assert np.all(dis < 1e-15 * np.abs(c * ysd + ymu).max())  # only the rounding of the mean

@@ -38,3 +38,26 @@ def test_mean_abs_error_and_transform():
     assert np.allclose(Z[:, 1], X[:, 1] / X[:, 3]) and np.allclose(Z[:, 2], X[:, 2] / X[:, 3])
     assert np.allclose(Z[:, 3], np.log(X[:, 3])) and np.allclose(Z[:, 4], np.log(X[:, 4]))
     assert np.array_equal(Z[:, [0, 5, 6, 7]], X[:, [0, 5, 6, 7]])
+
+
+def test_combined_threshold_keeps_combined_error_at_most_ssa():
+    """The combined threshold accepts, by increasing disagreement, the
+    longest prefix whose network errors do not exceed the SSA's in sum: the
+    combined error on those sets is then <= the SSA's, and one more set would
+    break it."""
+    dis = np.array([0.1, 0.2, 0.3, 0.4, 0.5])
+    e_nn = np.array([1.0, 3.0, 1.0, 9.0, 0.0])
+    e_ssa = np.array([2.0, 2.0, 2.0, 2.0, 2.0])
+    # running sums of e_nn - e_ssa: -1, 0, -1, 6, 4
+    assert S.choose_threshold_combined(dis, e_nn, e_ssa) == 0.3
+    assert S.choose_threshold_combined(dis, e_nn + 5, e_ssa) == -np.inf
+    rng = np.random.default_rng(4)
+    dis = rng.random(400)
+    e_ssa = 1.0 + 0.2 * rng.random(400)
+    e_nn = 2.0 * dis + 0.3 * rng.random(400)
+    th = S.choose_threshold_combined(dis, e_nn, e_ssa)
+    acc = dis <= th
+    comb = np.where(acc, e_nn, e_ssa)
+    assert acc.any() and comb.mean() <= e_ssa.mean() + 1e-12
+    nxt = np.sort(dis[~acc])
+    assert all(np.where(dis <= x, e_nn, e_ssa).mean() > e_ssa.mean() for x in nxt[:1])
