@@ -404,6 +404,19 @@ int siminf_mlp_ensemble_predict(siminf_mlp *const *nets, int32_t members, const 
                                 const float *y_mean, const float *y_std, float *Y, float *disagreement,
                                 void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as siminf_mlp_ensemble_predict, with the members x B x N
+ * workspace in a fixed array of 2^22 floats (16 MiB) in device memory that
+ * the library keeps on each device until the process ends; no allocation of
+ * any kind.  members x B x N above 2^22 returns SIMINF_E_UNSUPPORTED before
+ * any work is enqueued.  Every call on one device shares that array:
+ * calls that overlap on one device (other streams or threads) race and must
+ * be serialised by the caller. */
+int siminf_mlp_ensemble_predict_static(siminf_mlp *const *nets, int32_t members, const float *X, int32_t B,
+                                       const float *y_mean, const float *y_std, float *Y, float *disagreement,
+                                       void *hip_stream);
+
 /* C[M][N] (float32, row stride ldc) = A B with bfloat16 operands (uint16_t
  * bit patterns): A is M x K, stored A[m*lda + k] (a_trans = 0) or
  * A[k*lda + m] (a_trans = 1); B is K x N, stored B[n*ldb + k] (b_trans = 0)

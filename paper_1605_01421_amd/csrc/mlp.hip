@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -474,6 +475,36 @@ int ensemble_check(siminf_mlp* const* nets, int K, const float* X, int B, const 
     }
     return SIMINF_OK;
 }
+// The workspace of siminf_mlp_ensemble_predict_static, for callers that
+// cannot allocate: a fixed array in device memory, one per device (each GPU
+// the library runs on holds it until the process ends).  In host code the
+// array's name is not a device address: its address on the current device
+// comes from hipGetSymbolAddress, taken once per device.
+constexpr size_t SCRATCH_FLOATS = (size_t)1 << 22;  // 16 MiB
+__device__ __align__(256) float scratch[SCRATCH_FLOATS];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mutex;
+float* scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The current device's copy of `scratch`, or nullptr (and *rc set).
+float* scratch_on_current_device(int* rc) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES) {
+        *rc = SIMINF_E_DEVICE;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            *rc = SIMINF_E_DEVICE;
+            return nullptr;
+        }
+        scratch_ptr[dev] = (float*)ptr;
+    }
+    return scratch_ptr[dev];
+}
 }  // namespace
 
 extern "C" {
@@ -659,6 +690,18 @@ int siminf_mlp_ensemble_predict(siminf_mlp* const* nets, int32_t members, const 
     rc = ensemble_predict(nets, members, X, B, y_mean, y_std, Y, disagreement, st, work);
     if (hipFreeAsync(work, st) != hipSuccess && rc == SIMINF_OK) rc = SIMINF_E_DEVICE;
     return rc;
+}
+
+int siminf_mlp_ensemble_predict_static(siminf_mlp* const* nets, int32_t members, const float* X, int32_t B,
+                                       const float* y_mean, const float* y_std, float* Y, float* disagreement,
+                                       void* hip_stream) {
+    int rc = ensemble_check(nets, members, X, B, y_mean, y_std, Y, disagreement);
+    if (rc) return rc;
+    const size_t n = (size_t)members * B * nets[0]->dims[nets[0]->L];
+    if (n > SCRATCH_FLOATS) return SIMINF_E_UNSUPPORTED;
+    float* work = scratch_on_current_device(&rc);
+    if (!work) return rc;
+    return ensemble_predict(nets, members, X, B, y_mean, y_std, Y, disagreement, (hipStream_t)hip_stream, work);
 }
 
 int siminf_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t a_trans,

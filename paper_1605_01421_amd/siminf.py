@@ -86,6 +86,8 @@ SIGNATURES = {
                                         ctypes.c_float, _P]),
     "siminf_mlp_destroy": (None, [_P]),
     "siminf_mlp_ensemble_predict": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "siminf_mlp_ensemble_predict_static": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P, _P,
+                                                          _P]),
     "siminf_gemm_bf16": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                         ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                         _P]),
@@ -441,16 +443,22 @@ class MLP:
             raise SiminfError(rc, "siminf_mlp_adamw")
 
 
-def ensemble_predict(nets, X, y_mean, y_std, hip_stream=None):
-    """siminf_mlp_ensemble_predict: mean prediction (B, N) and disagreement
-    (B,) of the networks `nets` (MLP objects) on X (B, dims[0]); y_mean,
-    y_std are float32 CUDA tensors of the output width.  Torch tensors."""
+def ensemble_predict(nets, X, y_mean, y_std, hip_stream=None, static=False, out=None):
+    """siminf_mlp_ensemble_predict (static=True: the variant that allocates
+    nothing, siminf_mlp_ensemble_predict_static): mean prediction (B, N) and
+    disagreement (B,) of the networks `nets` (MLP objects) on X (B, dims[0]);
+    y_mean, y_std are float32 CUDA tensors of the output width.  Torch
+    tensors; `out` = (Y, dis) preallocated tensors to write into."""
     import torch
     B, N = X.shape[0], nets[0].dims[-1]
-    Y = torch.empty((B, N), dtype=torch.float32, device=X.device)
-    dis = torch.empty((B,), dtype=torch.float32, device=X.device)
+    if out is None:
+        Y = torch.empty((B, N), dtype=torch.float32, device=X.device)
+        dis = torch.empty((B,), dtype=torch.float32, device=X.device)
+    else:
+        Y, dis = out
     arr = (ctypes.c_void_p * len(nets))(*[n._h.value for n in nets])
-    rc = load().siminf_mlp_ensemble_predict(ctypes.cast(arr, ctypes.c_void_p), len(nets),
+    fn = load().siminf_mlp_ensemble_predict_static if static else load().siminf_mlp_ensemble_predict
+    rc = fn(ctypes.cast(arr, ctypes.c_void_p), len(nets),
                                             ctypes.c_void_p(X.data_ptr()), B,
                                             ctypes.c_void_p(y_mean.data_ptr()), ctypes.c_void_p(y_std.data_ptr()),
                                             ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(dis.data_ptr()),
