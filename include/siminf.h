@@ -76,6 +76,18 @@ enum {
  *    beta_1..beta_4).  S->I at upsilon*phi*S, I->S at gamma*I; after each day
  *    phi <- phi*(1-beta_q) + alpha*I/(S+I) (0 for an empty node), q = first
  *    season whose end is >= the day of year of the new day (else season 1).
+ * SISE_SP (sec. 4.2, eq. envInfPressure-local-spread): SISE with the spatial
+ *    coupling of phi among proximal nodes; gdata = (upsilon, gamma, alpha,
+ *    beta_1..beta_4, D), the sparse distance matrix in the spec's nb_*
+ *    fields.  After each day
+ *      phi_i <- (phi_i*(1-beta_q) + alpha*I_i/N_i) + c_i,
+ *      c_i = sum over i's neighbours k, in stored order, of
+ *            ((phi_k*N_k - phi_i*N_i) / N_i) * (D / d_ik),
+ *    all phi taken before the day's update, N = S+I after the day's events
+ *    (the alpha term and c_i are 0 for an empty node).  The nodes then
+ *    depend on each other every day: such a model runs only in the dataflow
+ *    kernel (all its node wavefronts resident on the device at once, else
+ *    SIMINF_E_UNSUPPORTED) and alone in its handle (no other model group).
  * BIRTH_DEATH: Nc=1, Nt=2, gdata=(b, d): X->2X at b*X, X->0 at d*X.
  * IMMIGRATION_DEATH: Nc=1, Nt=2, gdata=(kappa, mu): 0->X at kappa, X->0 at mu*X.
  * Arithmetic is IEEE binary64 in the operation order written above. */
@@ -84,7 +96,8 @@ enum {
     SIMINF_SIS = 1,
     SIMINF_SISE = 2,
     SIMINF_BIRTH_DEATH = 3,
-    SIMINF_IMMIGRATION_DEATH = 4
+    SIMINF_IMMIGRATION_DEATH = 4,
+    SIMINF_SISE_SP = 5
 };
 
 /* event type codes (Table 2) */
@@ -124,6 +137,14 @@ typedef struct {
     const int32_t *ev_type, *ev_time, *ev_node, *ev_dest, *ev_n, *ev_select, *ev_shift;
     const double *ev_prop;
     const int32_t *E, *N;
+    /* SISE_SP only (ignored otherwise): the distance matrix of section 4.2
+     * (distance_matrix() with its cutoff) in compressed columns -- node i's
+     * neighbours are nb_idx[nb_ptr[i] .. nb_ptr[i+1]-1] (0-based, the same
+     * run) at distances nb_dist > 0 in the same positions; nb_ptr has Nn+1
+     * entries, nb_ptr[0] = 0, nb_ptr[Nn] = Nnb. */
+    int32_t Nnb;
+    const int32_t *nb_ptr, *nb_idx;
+    const double *nb_dist;
 } siminf_spec;
 
 /* Launch and recording options; a zeroed struct (or NULL) gives defaults. */

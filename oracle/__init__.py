@@ -13,7 +13,9 @@ the ``cpu_baseline`` leg of ``bench.py`` may import it.
 
 This module only marshals numpy arrays to the C oracle through ctypes.  A
 model specification is any object with the attributes ``model, S, G, u0, v0,
-ldata, gdata, tspan, E, N, events`` (see ``run``).
+ldata, gdata, tspan, E, N, events`` (see ``run``), and for SISe_sp
+``neighbours`` = dict(ptr, idx, dist), the sparse distance matrix in
+compressed columns.
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "siminf_oracle.c")
 _LIB = os.path.join(_HERE, "libsiminf_oracle.so")
 
-MODELS = {"SIR": 0, "SIS": 1, "SISE": 2, "BIRTH_DEATH": 3, "IMMIGRATION_DEATH": 4}
+MODELS = {"SIR": 0, "SIS": 1, "SISE": 2, "BIRTH_DEATH": 3, "IMMIGRATION_DEATH": 4, "SISE_SP": 5}
 ERRORS = {0: "ok", -1: "E_ARG", -2: "E_UNSUPPORTED", -3: "E_ALLOC",
           -5: "E_NEG_STATE", -6: "E_BAD_RATE", -7: "E_EVENT_OVERDRAW",
           -8: "E_EVENT_INDEX", -9: "E_PTS", -10: "E_STEP_LIMIT"}
@@ -56,7 +58,9 @@ class _Model(ctypes.Structure):
         ("ev_node", ctypes.c_void_p), ("ev_dest", ctypes.c_void_p),
         ("ev_n", ctypes.c_void_p), ("ev_select", ctypes.c_void_p),
         ("ev_shift", ctypes.c_void_p), ("ev_prop", ctypes.c_void_p),
-        ("E", ctypes.c_void_p), ("N", ctypes.c_void_p)]
+        ("E", ctypes.c_void_p), ("N", ctypes.c_void_p),
+        ("Nnb", ctypes.c_int32), ("nb_ptr", ctypes.c_void_p), ("nb_idx", ctypes.c_void_p),
+        ("nb_dist", ctypes.c_void_p)]
 
 
 _lib = None
@@ -135,6 +139,15 @@ def run(spec, seed: int, stream: int = 0, nthreads: int | None = None) -> dict:
     for nm in names[1:]:
         setattr(m, "ev_" + nm, _ptr(keep["ev_" + nm]))
     m.ev_prop = _ptr(keep["ev_prop"])
+    nb = getattr(spec, "neighbours", None)
+    if nb is not None:
+        keep["nb_ptr"] = _c(nb["ptr"], np.int32)
+        keep["nb_idx"] = _c(nb["idx"], np.int32)
+        keep["nb_dist"] = _c(nb["dist"], np.float64)
+        m.Nnb = keep["nb_idx"].size
+        m.nb_ptr = _ptr(keep["nb_ptr"])
+        m.nb_idx = _ptr(keep["nb_idx"])
+        m.nb_dist = _ptr(keep["nb_dist"])
     Ntspan = keep["tspan"].size
     U = np.zeros((Ntspan, Nn, Nc), dtype=np.int32)
     V = np.zeros((Ntspan, Nn, m.Nv), dtype=np.float64)

@@ -79,6 +79,7 @@
 #define MODEL_SISE 2
 #define MODEL_BIRTH_DEATH 3
 #define MODEL_IMMIGRATION_DEATH 4
+#define MODEL_SISE_SP 5
 
 /* event type codes of Table 2 */
 #define EV_EXIT 0
@@ -99,6 +100,12 @@ typedef struct {
         *ev_shift;
     const double *ev_prop;
     const int32_t *E, *N;
+    /* SISe_sp: the sparse distance matrix of section 4.2 in compressed
+     * columns: node i's neighbours are nb_idx[nb_ptr[i] .. nb_ptr[i+1]),
+     * at distances nb_dist (same positions).  Unused by the other models. */
+    int32_t Nnb;
+    const int32_t *nb_ptr, *nb_idx;
+    const double *nb_dist;
 } oracle_model;
 
 /* ======================================================================
@@ -266,7 +273,8 @@ static double rate_fn(int model, int j, const int32_t *u, const double *v,
             return (gd[0] * S) * I;
         return gd[1] * I;
     }
-    case MODEL_SISE: {
+    case MODEL_SISE:
+    case MODEL_SISE_SP: {
         /* eq. vtectrans: S -> I at upsilon*phi per susceptible,
          * I -> S at gamma per infected. gdata = (upsilon, gamma, ...). */
         double S = (double)u[0], I = (double)u[1];
@@ -304,6 +312,9 @@ static int model_dims(int model, int *Nc, int *Nt, int *Nv, int *Nld,
     case MODEL_SISE:
         *Nc = 2; *Nt = 2; *Nv = 1; *Nld = 4; *Ngd = 7;
         return 1;
+    case MODEL_SISE_SP:
+        *Nc = 2; *Nt = 2; *Nv = 1; *Nld = 4; *Ngd = 8;
+        return 1;
     case MODEL_BIRTH_DEATH:
     case MODEL_IMMIGRATION_DEATH:
         *Nc = 1; *Nt = 2; *Nv = 0; *Nld = 0; *Ngd = 2;
@@ -326,6 +337,49 @@ static int day_of_year(int64_t T) {
  * no spatial coupling), i.e. phi' = phi*(1-beta_q) + alpha*I/N, where the
  * season q is the first k with day-of-year <= end_k (ldata), else season 0;
  * I/N is taken as 0 for an empty node. */
+/* SISe_sp (section 4.2, eq. envInfPressure-local-spread): one explicit-
+ * Euler step of unit length of
+ *   d phi_i/dt = alpha I_i/N_i + sum_k (phi_k N_k - phi_i N_i)/N_i * D/d_ik
+ *                - beta(t) phi_i
+ * taken, in this order, as
+ *   phi_i' = (phi_i (1 - beta_q) + alpha I_i / N_i) + c_i,
+ *   c_i = sum over the neighbours k in stored order of
+ *         ((phi_k N_k - phi_i N_i) / N_i) * (D / d_ik),
+ * with every phi the value before this step (all nodes are advanced from
+ * the same state) and N = S + I after the day's events; the alpha and the
+ * coupling terms are 0 for an empty node.  D = gdata[7]. */
+static int pts_sise_sp(const oracle_model *m, double *v_new, const int32_t *u, const double *v, int i,
+                       int64_t T) {
+    const double *ld = m->ldata + (size_t)i * m->Nld;
+    const double *gd = m->gdata;
+    const int32_t *ui = u + (size_t)i * 2;
+    int doy = day_of_year(T);
+    int q = 0;
+    for (int k = 3; k >= 0; --k)
+        if ((double)doy <= ld[k])
+            q = k;
+    double beta = gd[3 + q];
+    double a = v[i] * (1.0 - beta);
+    int32_t Ni = ui[0] + ui[1];
+    double b = 0.0;
+    double c = 0.0;
+    if (Ni > 0) {
+        b = (gd[2] * (double)ui[1]) / (double)Ni;
+        for (int e = m->nb_ptr[i]; e < m->nb_ptr[i + 1]; ++e) {
+            int k = m->nb_idx[e];
+            int32_t Nk = u[(size_t)k * 2] + u[(size_t)k * 2 + 1];
+            double flow = (v[k] * (double)Nk) - (v[i] * (double)Ni);
+            double term = (flow / (double)Ni) * (gd[7] / m->nb_dist[e]);
+            c = c + term;
+        }
+    }
+    double phi = (a + b) + c;
+    if (!isfinite(phi))
+        return OR_E_PTS;
+    v_new[0] = phi;
+    return 0;
+}
+
 static int pts_fn(int model, double *v_new, const int32_t *u, const double *v,
                   const double *ld, const double *gd, int Nv, int64_t T) {
     if (model == MODEL_SISE) {
@@ -480,6 +534,18 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
         return err[0] = OR_E_ARG;
     const int Nn = m->Nn;
     const int Ntspan = m->Ntspan;
+    if (m->model == MODEL_SISE_SP) {
+        /* the neighbour lists: within the nodes, positive finite distances */
+        if (!m->nb_ptr || (m->Nnb > 0 && (!m->nb_idx || !m->nb_dist)) || m->nb_ptr[0] != 0 ||
+            m->nb_ptr[Nn] != m->Nnb)
+            return err[0] = OR_E_ARG;
+        for (int i = 0; i < Nn; ++i)
+            if (m->nb_ptr[i + 1] < m->nb_ptr[i])
+                return err[0] = OR_E_ARG;
+        for (int e = 0; e < m->Nnb; ++e)
+            if (m->nb_idx[e] < 0 || m->nb_idx[e] >= Nn || !(m->nb_dist[e] > 0.0) || !isfinite(m->nb_dist[e]))
+                return err[0] = OR_E_ARG;
+    }
     for (int k = 1; k < Ntspan; ++k)
         if (!(m->tspan[k] > m->tspan[k - 1]))
             return err[0] = OR_E_ARG;
@@ -488,6 +554,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
 
     int32_t *u = malloc(sizeof(int32_t) * (size_t)Nc * (Nn ? Nn : 1));
     double *v = malloc(sizeof(double) * (size_t)(Nv ? Nv : 1) * (Nn ? Nn : 1));
+    double *v_next = malloc(sizeof(double) * (size_t)(Nv ? Nv : 1) * (Nn ? Nn : 1));
     int *order = malloc(sizeof(int) * (size_t)(m->Nev ? m->Nev : 1));
     int *e1_start = calloc((size_t)Nn + 1, sizeof(int));
     int *e1_list = malloc(sizeof(int) * (size_t)(m->Nev ? m->Nev : 1));
@@ -496,9 +563,9 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
     uint64_t *node_err = malloc(sizeof(uint64_t) * (size_t)(Nn ? Nn : 1));
     uint64_t *node_trans = calloc((size_t)(Nn ? Nn : 1), sizeof(uint64_t));
     uint64_t *node_events = calloc((size_t)(Nn ? Nn : 1), sizeof(uint64_t));
-    if (!u || !v || !order || !e1_start || !e1_list || !e1_cursor ||
+    if (!u || !v || !v_next || !order || !e1_start || !e1_list || !e1_cursor ||
         !e2_list || !node_err || !node_trans || !node_events) {
-        free(u); free(v); free(order); free(e1_start); free(e1_list);
+        free(u); free(v); free(v_next); free(order); free(e1_start); free(e1_list);
         free(e1_cursor); free(e2_list); free(node_err); free(node_trans);
         free(node_events);
         return err[0] = OR_E_ALLOC;
@@ -687,19 +754,33 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
         }
 
         /* ---- post time step (Appendix A) ------------------------------- */
+        if (m->model == MODEL_SISE_SP) {
+            /* every node's step reads its neighbours' values before the
+             * step: new values go to a second buffer first */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
-        for (int i = 0; i < Nn; ++i) {
-            double vnew[64];
-            node_err[i] = NOERR;
-            int rc = pts_fn(m->model, vnew, u + (size_t)i * Nc,
-                            v + (size_t)i * Nv, m->ldata + (size_t)i * m->Nld,
-                            m->gdata, Nv, Tint);
-            if (rc < 0) {
-                node_err[i] = make_key(b, PH_PTS, i, OR_E_PTS);
-                continue;
+            for (int i = 0; i < Nn; ++i) {
+                node_err[i] = NOERR;
+                if (pts_sise_sp(m, v_next + i, u, v, i, Tint) < 0) {
+                    node_err[i] = make_key(b, PH_PTS, i, OR_E_PTS);
+                    v_next[i] = v[i];
+                }
             }
-            for (int k = 0; k < Nv; ++k)
-                v[(size_t)i * Nv + k] = vnew[k];
+            memcpy(v, v_next, sizeof(double) * (size_t)Nn);
+        } else {
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (int i = 0; i < Nn; ++i) {
+                double vnew[64];
+                node_err[i] = NOERR;
+                int rc = pts_fn(m->model, vnew, u + (size_t)i * Nc,
+                                v + (size_t)i * Nv, m->ldata + (size_t)i * m->Nld,
+                                m->gdata, Nv, Tint);
+                if (rc < 0) {
+                    node_err[i] = make_key(b, PH_PTS, i, OR_E_PTS);
+                    continue;
+                }
+                for (int k = 0; k < Nv; ++k)
+                    v[(size_t)i * Nv + k] = vnew[k];
+            }
         }
         for (int i = 0; i < Nn; ++i)
             if (node_err[i] < phase_err)
@@ -733,7 +814,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
         counters[2] += node_events[i];
     }
 done:
-    free(u); free(v); free(order); free(e1_start); free(e1_list);
+    free(u); free(v); free(v_next); free(order); free(e1_start); free(e1_list);
     free(e1_cursor); free(e2_list); free(node_err); free(node_trans);
     free(node_events);
     return (int)err[0];

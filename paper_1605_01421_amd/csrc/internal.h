@@ -104,6 +104,19 @@ __host__ __device__ inline int xcd_block(int b, int b0, int nblk, int g) {
     return a + (r - rem) + (rem % XCDS) * g + rem / XCDS;
 }
 
+// What a node of a spatially coupled model posts for its neighbours each
+// day: its continuous state before the post-time step and its size after
+// the day's events; `day` (the day step, -1 before the run) is stored last
+// with release order and tells a reader the post is complete.  Two posts per
+// node (day parity): a node posts day b + 2 only after reading every
+// neighbour's day b + 1 post, which each neighbour makes only after reading
+// this node's day b post.
+struct CplPost {
+    double phi;
+    int32_t n;
+    int32_t day;
+};
+
 struct KParams {
     int32_t n;        // nodes in the group
     int32_t nb;       // number of unit-time steps
@@ -165,6 +178,13 @@ struct KParams {
     const int4* lchunks;         // [nlchunks] x = first node, y = end, z = run
     int32_t lq_batch;            // lanes that wait at their day's end before the
                                  // wavefront closes their days together
+    int32_t coupled;             // spatial coupling of the post-time step (SISe_sp):
+    const int32_t* cpl_off;      //   [n+1] each node's neighbours (internal order), then
+                                 //         the nodes that list it but that it does not list
+    const int32_t* cpl_fend;     //   [n]   end of the first part (the summed neighbours)
+    const int32_t* cpl_idx;      //   [nnz] neighbour
+    const double* cpl_w;         //   [nnz] coupling weight D / distance
+    CplPost* cpl_post;           //   [2][n] the day's posts
 };
 
 // Lane-queue kernel: recording slots per wavefront (a slot accumulates one

@@ -10,7 +10,7 @@
 
 namespace siminf {
 
-enum ModelId { M_SIR = 0, M_SIS = 1, M_SISE = 2, M_BIRTH_DEATH = 3, M_IMMIGRATION_DEATH = 4 };
+enum ModelId { M_SIR = 0, M_SIS = 1, M_SISE = 2, M_BIRTH_DEATH = 3, M_IMMIGRATION_DEATH = 4, M_SISE_SP = 5 };
 
 __device__ __forceinline__ double pick(bool c, double a, double b) { return c ? a : b; }
 
@@ -18,6 +18,7 @@ __device__ __forceinline__ double pick(bool c, double a, double b) { return c ? 
 // (Appendix C listing); I -> R at gamma I.  gdata = (beta, gamma).
 struct ModelSIR {
     static constexpr int ID = M_SIR, NC = 3, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    static constexpr bool COUPLED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -40,6 +41,7 @@ struct ModelSIR {
 // SIS (eqs. sirtrans, SIRstoich): S + I -> 2I at beta S I; I -> S at gamma I.
 struct ModelSIS {
     static constexpr int ID = M_SIS, NC = 2, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    static constexpr bool COUPLED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -66,6 +68,7 @@ struct ModelSIS {
 // gdata = (upsilon, gamma, alpha, beta_1, beta_2, beta_3, beta_4).
 struct ModelSISe {
     static constexpr int ID = M_SISE, NC = 2, NT = 2, NV = 1, NLD = 4, NGD = 7;
+    static constexpr bool COUPLED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double* v, const double*,
                                                   const double* gd) {
@@ -104,9 +107,59 @@ struct ModelSISe {
     }
 };
 
+// SISe_sp (section 4.2): SISe with the spatial coupling of the environmental
+// pressure among proximal nodes.  The rates are SISe's; the post-time step
+// is one explicit-Euler step of unit length of eq.
+// envInfPressure-local-spread,
+//   phi_i <- (phi_i (1 - beta_q) + alpha I_i / N_i) + c_i,
+//   c_i = sum over the neighbours k, in stored order, of
+//         ((phi_k N_k - phi_i N_i) / N_i) * w_ik,   w_ik = D / d_ik,
+// every phi taken before the step and N = S + I after the day's events; the
+// alpha term and c_i are 0 for an empty node.  The kernel gathers c_i from
+// the neighbours (coupling_term) and hands it to pts_coupled; only the
+// dataflow kernel, where every node is resident, runs this model.
+// gdata = (upsilon, gamma, alpha, beta_1, beta_2, beta_3, beta_4, D).
+struct ModelSISeSp {
+    static constexpr int ID = M_SISE_SP, NC = 2, NT = 2, NV = 1, NLD = 4, NGD = 8;
+    static constexpr bool COUPLED = true;
+    template <int J>
+    __device__ static __forceinline__ double rate(const int32_t* u, const double* v, const double* ld,
+                                                  const double* gd) {
+        return ModelSISe::template rate<J>(u, v, ld, gd);
+    }
+    __device__ static __forceinline__ double coupling_term(double phi_k, int32_t n_k, double phi_i, int32_t n_i,
+                                                           double w) {
+        const double flow = (phi_k * (double)n_k) - (phi_i * (double)n_i);
+        return (flow / (double)n_i) * w;
+    }
+    __device__ static __forceinline__ bool pts_coupled(double* v, const int32_t* u, const double* ld,
+                                                       const double* gd, int64_t day, double c) {
+        const int64_t dm = day - 1;
+        int64_t r;
+        if (dm >= 0 && dm <= 0x7FFFFFFF) {
+            r = (int64_t)((uint32_t)dm % 365u);
+        } else {
+            r = dm % 365;
+            if (r < 0) r += 365;
+        }
+        const double doy = (double)(r + 1);
+        const double decay = pick(doy <= ld[0], gd[3],
+                                  pick(doy <= ld[1], gd[4],
+                                       pick(doy <= ld[2], gd[5], pick(doy <= ld[3], gd[6], gd[3]))));
+        const double kept = v[0] * (1.0 - decay);
+        const int32_t total = u[0] + u[1];
+        const double shed = total > 0 ? (gd[2] * (double)u[1]) / (double)total : 0.0;
+        const double phi = (kept + shed) + c;
+        v[0] = phi;
+        return isfinite(phi);
+    }
+    __device__ static __forceinline__ bool pts_fixed(const double*, const int32_t*) { return false; }
+};
+
 // Linear birth-death: X -> 2X at b X, X -> 0 at d X.  gdata = (b, d).
 struct ModelBirthDeath {
     static constexpr int ID = M_BIRTH_DEATH, NC = 1, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    static constexpr bool COUPLED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -123,6 +176,7 @@ struct ModelBirthDeath {
 // Immigration-death: 0 -> X at kappa, X -> 0 at mu X.  gdata = (kappa, mu).
 struct ModelImmigrationDeath {
     static constexpr int ID = M_IMMIGRATION_DEATH, NC = 1, NT = 2, NV = 0, NLD = 0, NGD = 2;
+    static constexpr bool COUPLED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -150,6 +204,7 @@ inline bool model_shape(int id, ModelShape* s) {
         case M_SISE: *s = {2, 2, 1, 4, 7}; return true;
         case M_BIRTH_DEATH: *s = {1, 2, 0, 0, 2}; return true;
         case M_IMMIGRATION_DEATH: *s = {1, 2, 0, 0, 2}; return true;
+        case M_SISE_SP: *s = {2, 2, 1, 4, 8}; return true;
     }
     return false;
 }

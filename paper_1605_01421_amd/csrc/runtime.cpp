@@ -144,6 +144,17 @@ int validate_spec(const siminf_spec& s, int64_t* bad_event) {
     if (s.Nn > 0 && s.Nld > 0 && !s.ldata) return SIMINF_E_ARG;
     for (int k = 0; k < s.Ntspan; ++k)
         if (!std::isfinite(s.tspan[k]) || (k > 0 && !(s.tspan[k] > s.tspan[k - 1]))) return SIMINF_E_ARG;
+    if (s.model == M_SISE_SP) {
+        // the sparse distance matrix: compressed columns within the run
+        if (!s.nb_ptr || s.Nnb < 0 || (s.Nnb > 0 && (!s.nb_idx || !s.nb_dist)) || s.nb_ptr[0] != 0 ||
+            s.nb_ptr[s.Nn] != s.Nnb)
+            return SIMINF_E_ARG;
+        for (int i = 0; i < s.Nn; ++i)
+            if (s.nb_ptr[i + 1] < s.nb_ptr[i]) return SIMINF_E_ARG;
+        for (int e = 0; e < s.Nnb; ++e)
+            if (s.nb_idx[e] < 0 || s.nb_idx[e] >= s.Nn || !(s.nb_dist[e] > 0.0) || !std::isfinite(s.nb_dist[e]))
+                return SIMINF_E_ARG;
+    }
     for (int64_t i = 0; i < (int64_t)s.Nn * s.Nc; ++i)
         if (s.u0[i] < 0) return SIMINF_E_ARG;
     if (s.Nev > 0) {
@@ -255,7 +266,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     KParams& p = g.p;
     p.lane_queue = 0;
     g.lq_chunk = 0;
-    if (lq_chunk > 0 && g.n_e2 == 0) {
+    if (lq_chunk > 0 && g.n_e2 == 0 && !p.coupled) {
         const int cus = device_cus(m);
         if (cus <= 0) return SIMINF_E_DEVICE;
         if (block == 0) block = 256;
@@ -319,6 +330,9 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         return SIMINF_OK;
     }
     if (lq_chunk > 0) return SIMINF_E_UNSUPPORTED;
+    // the coupled post-time step: the dataflow kernel only, every node resident
+    const bool coupled = p.coupled != 0;
+    if (coupled && want_mode == 1) return SIMINF_E_UNSUPPORTED;
     const int n = g.n;
     const int cus = device_cus(m);
     if (cus <= 0) return SIMINF_E_DEVICE;
@@ -331,11 +345,11 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     // waves per SIMD the extra, unused last draw of each node-day only costs
     const int simd_lanes = cus * 4 * WAVE;
     p.pipeline = pipeline == 1 ? 1 : pipeline == 2 ? 0 : (n <= simd_lanes ? 1 : 0);
-    if (block == 0) block = g.n_e2 > 0 ? 64 : 256;
+    if (block == 0) block = g.n_e2 > 0 || coupled ? 64 : 256;
     const int wpb = block / WAVE;
     int mode = MODE_FREE, blocks = 0;
     size_t shmem = 0;
-    if (g.n_e2 > 0) {
+    if (g.n_e2 > 0 || coupled) {
         if (want_mode == 0 || want_mode == 2) {
             int nb = nbig;
             int ng = std::min(ngrp, n - nb);
@@ -354,7 +368,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
                 nbig = nb;
                 ngrp = std::min(ng, n - nb);
                 blocks = std::max(1, need(nb, ngrp));
-            } else if (want_mode == 2) {
+            } else if (want_mode == 2 || coupled) {
                 return SIMINF_E_UNSUPPORTED;
             }
         }
@@ -519,7 +533,9 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
     bool any_e2 = false;
     for (int s = 0; s < nspecs; ++s)
         for (int e = 0; e < specs[s].Nev; ++e) any_e2 |= specs[s].ev_type[e] == SIMINF_EXTTRANS;
-    if (any_e2 && m->groups.size() > 1) {
+    bool any_coupled = false;
+    for (int s = 0; s < nspecs; ++s) any_coupled |= specs[s].model == M_SISE_SP;
+    if ((any_e2 || any_coupled) && m->groups.size() > 1) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -659,6 +675,47 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
             node_idx[k] = nr.idx;
             node_ord[k] = m->runs[nr.run].noff + nr.idx;
             pos[m->runs[nr.run].noff + nr.idx] = k;
+        }
+        // spatial coupling: each node's neighbours at their internal positions
+        // in stored order, with the weight D / d of each pair (one IEEE
+        // division, as the model writes it), then the nodes that list it but
+        // that it does not list (waited for only)
+        std::vector<int32_t> cpl_off, cpl_fend, cpl_idx;
+        std::vector<double> cpl_w;
+        const bool coupled = g.model == M_SISE_SP;
+        if (coupled) {
+            std::vector<std::vector<int32_t>> readers(n);
+            for (int k = 0; k < n; ++k) {
+                const NodeRef& nr = nodes[k];
+                const siminf_spec& sp2 = specs[m->runs[nr.run].spec];
+                for (int e = sp2.nb_ptr[nr.idx]; e < sp2.nb_ptr[nr.idx + 1]; ++e)
+                    readers[pos[m->runs[nr.run].noff + sp2.nb_idx[e]]].push_back(k);
+            }
+            cpl_off.assign(n + 1, 0);
+            cpl_fend.assign(n, 0);
+            std::vector<int32_t> fwd;
+            for (int k = 0; k < n; ++k) {
+                const NodeRef& nr = nodes[k];
+                const siminf_spec& sp2 = specs[m->runs[nr.run].spec];
+                fwd.clear();
+                for (int e = sp2.nb_ptr[nr.idx]; e < sp2.nb_ptr[nr.idx + 1]; ++e) {
+                    const int32_t j = pos[m->runs[nr.run].noff + sp2.nb_idx[e]];
+                    cpl_idx.push_back(j);
+                    cpl_w.push_back(sp2.gdata[7] / sp2.nb_dist[e]);
+                    fwd.push_back(j);
+                }
+                cpl_fend[k] = (int32_t)cpl_idx.size();
+                std::sort(fwd.begin(), fwd.end());
+                std::vector<int32_t>& rd = readers[k];
+                std::sort(rd.begin(), rd.end());
+                rd.erase(std::unique(rd.begin(), rd.end()), rd.end());
+                for (int32_t j : rd)
+                    if (!std::binary_search(fwd.begin(), fwd.end(), j)) {
+                        cpl_idx.push_back(j);
+                        cpl_w.push_back(0.0);
+                    }
+                cpl_off[k + 1] = (int32_t)cpl_idx.size();
+            }
         }
         // events: E1 in node-major CSR, E2 grouped by step and conflict level
         struct Ev {
@@ -880,6 +937,19 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         p.ctrl = m->d_ctrl;
         p.rp = m->d_rp;
         p.group = (int)gi;
+        p.coupled = coupled ? 1 : 0;
+        if (coupled) {
+            int32_t *d_coff, *d_cfend, *d_cidx;
+            double* d_cw;
+            if (to_device(m->owned, cpl_off, &d_coff) || to_device(m->owned, cpl_fend, &d_cfend) ||
+                to_device(m->owned, cpl_idx, &d_cidx) || to_device(m->owned, cpl_w, &d_cw) ||
+                alloc_device(m->owned, (size_t)2 * n, &p.cpl_post))
+                return hip_fail(m);
+            p.cpl_off = d_coff;
+            p.cpl_fend = d_cfend;
+            p.cpl_idx = d_cidx;
+            p.cpl_w = d_cw;
+        }
         if (g.n_e2 > 0) {
             // live state for the transfer kernels (both variants)
             if (alloc_device(m->owned, (size_t)nc * n, &p.u) || alloc_device(m->owned, (size_t)std::max(nv, 1) * n, &p.v) ||
@@ -889,7 +959,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         }
         g.node_run = node_run;
         int lq = 0;
-        if (g.n_e2 == 0) {
+        if (g.n_e2 == 0 && !coupled) {
             // the lane-queue chunk table: at most one chunk per run and per 64 nodes more
             g.chunk_cap = (int)grp_runs.size() + n / 64 + 1;
             if (alloc_device(m->owned, (size_t)g.chunk_cap, &g.d_chunks)) return hip_fail(m);
@@ -1277,7 +1347,7 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     // the lane queue (models without external transfers), at three block
     // sizes and two chunk sizes, unless an option fixes the lane layout
     bool free_only = true;
-    for (const Group& g : m->groups) free_only = free_only && g.n_e2 == 0;
+    for (const Group& g : m->groups) free_only = free_only && g.n_e2 == 0 && !g.p.coupled;
     const bool shaped = m->opt.lanes != 0 || m->opt.wide != 0 || m->opt.group != 0 || m->opt.pack != 0;
     if (free_only && m->opt.lane_queue != 2 && (m->opt.lane_queue == 1 || !shaped)) {
         const int ch = m->opt.chunk > 0 ? m->opt.chunk : 512;

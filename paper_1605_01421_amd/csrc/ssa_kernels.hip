@@ -1235,6 +1235,64 @@ __device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long
     }
 }
 
+// The coupling sum of a spatially coupled post-time step (SISe_sp): every
+// node posts its continuous state before the step and its size after the
+// day's events, then adds up the coupling terms of its neighbours' posts in
+// stored order, waiting for each post.  Every node posts before it waits,
+// so every wait ends (all node wavefronts are resident in this kernel).
+// Posts alternate between two buffers by day parity.  A node also waits for
+// the day's posts of the nodes that read it (whether or not it reads them,
+// and whatever its size): it can then overwrite a buffer two days on only
+// after every reader has posted the next day, that is, has finished reading
+// the post it overwrites.
+// Called by every lane of the wavefront (the wait loop is wave-uniform);
+// `active` lanes carry a node, `owner` is the lane that posts for it, and
+// nodes that an error stopped keep posting their last state.  c is 0 for an
+// empty node.  A wait longer than the wall-clock limit abandons the run; an
+// earlier error lets the waits give up (the run's later results are
+// undefined).
+template <class M>
+__device__ __forceinline__ double coupled_sum(const KParams& p, const Node<M>& s, int k, int b, bool active,
+                                              bool owner) {
+    const int32_t ni = s.u[0] + s.u[1];
+    CplPost* post = p.cpl_post + (size_t)(b & 1) * p.n;
+    if (owner) {
+        post[k].phi = s.v[0];
+        post[k].n = ni;
+        __hip_atomic_store(&post[k].day, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    double c = 0.0;
+    int e = active ? p.cpl_off[k] : 0;
+    const int eend = active ? p.cpl_off[k + 1] : 0;
+    const int fend = active && ni > 0 ? p.cpl_fend[k] : e;
+    unsigned spins = 0;
+    WaitClock clock;
+    while (__any(e < eend)) {
+        bool moved = false;
+        if (e < eend) {
+            const int j = p.cpl_idx[e];
+            if (__hip_atomic_load(&post[j].day, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == b) {
+                if (e < fend) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    c = c + M::coupling_term(post[j].phi, post[j].n, s.v[0], ni, p.cpl_w[e]);
+                }
+                ++e;
+                moved = true;
+            }
+        }
+        if (!__any(moved) && (++spins & 255u) == 0) {
+            const bool quit = __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                              load_error_step(p.ctrl) < (uint64_t)b;
+            const bool late = __shfl(clock.expired(p.wait_ticks) ? 1 : 0, 0, WAVE) != 0;
+            if (late && (threadIdx.x & (WAVE - 1)) == 0)
+                __hip_atomic_store(&p.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__any(quit) || late) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return c;
+}
+
 template <class M, bool PIPE, bool GRP>
 __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     KParams p = pa;
@@ -1345,7 +1403,16 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
                 }
             }
         }
-        if (active && !dead) {
+        if constexpr (M::COUPLED) {
+            const double c = coupled_sum<M>(p, s, k, b, active, owner);
+            if (active && !dead) {
+                if (!M::pts_coupled(s.v, s.u, s.ld, s.gd, day, c)) {
+                    if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
+                    dead = true;
+                }
+                t.nd += owner ? 1 : 0;
+            }
+        } else if (active && !dead) {
             if (!M::pts(s.v, s.u, s.ld, s.gd, day)) {
                 if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
                 dead = true;
@@ -1514,6 +1581,8 @@ __global__ void init_kernel(KParams p, int nc, int nv, int first_rec, int reset_
         for (long long i = gtid; i < sums_len; i += nthreads) p.sums[i] = sums_init[i];
     if (p.mode == MODE_FLOW)
         for (int e = gtid; e < p.n_e2; e += nthreads) p.mail[e] = 0ull;
+    if (p.coupled)
+        for (int i = gtid; i < 2 * p.n; i += nthreads) p.cpl_post[i].day = -1;
     for (int k = gtid; k < p.n; k += nthreads) {
         if (p.mode == MODE_BARRIER) {
             for (int c = 0; c < nc; ++c) p.u[(size_t)c * p.n + k] = p.u0[(size_t)c * p.n + k];
@@ -1603,6 +1672,14 @@ const void* model_kernel(int model, int mode, int pipeline, bool grp, bool lq) {
         case M_SISE: return kernel_for<ModelSISe>(mode, pipeline, grp, lq);
         case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline, grp, lq);
         case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline, grp, lq);
+        case M_SISE_SP:
+            // the coupled post-time step exists in the dataflow kernel only
+            if (mode != MODE_FLOW || lq) return nullptr;
+            if (pipeline)
+                return grp ? (const void*)flow_kernel<ModelSISeSp, true, true>
+                           : (const void*)flow_kernel<ModelSISeSp, true, false>;
+            return grp ? (const void*)flow_kernel<ModelSISeSp, false, true>
+                       : (const void*)flow_kernel<ModelSISeSp, false, false>;
     }
     return nullptr;
 }
@@ -1611,7 +1688,7 @@ const void* model_kernel(int model, int mode, int pipeline, bool grp, bool lq) {
 
 hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st) {
-    int blocks = (int)((std::max(p.n, p.n_e2) + 255) / 256);
+    int blocks = (int)((std::max(p.coupled ? 2 * p.n : p.n, p.n_e2) + 255) / 256);
     if (sums_init) blocks = (int)std::max<long long>(blocks, (sums_len + 255) / 256);
     blocks = std::max(1, std::min(blocks, 4096));
     init_kernel<<<blocks, 256, 0, st>>>(p, nc, nv, first_rec, reset_ctrl ? 1 : 0, sums_init, sums_len);

@@ -42,7 +42,9 @@ class Spec(ctypes.Structure):
         ("ev_type", ctypes.c_void_p), ("ev_time", ctypes.c_void_p), ("ev_node", ctypes.c_void_p),
         ("ev_dest", ctypes.c_void_p), ("ev_n", ctypes.c_void_p), ("ev_select", ctypes.c_void_p),
         ("ev_shift", ctypes.c_void_p), ("ev_prop", ctypes.c_void_p),
-        ("E", ctypes.c_void_p), ("N", ctypes.c_void_p)]
+        ("E", ctypes.c_void_p), ("N", ctypes.c_void_p),
+        ("Nnb", ctypes.c_int32), ("nb_ptr", ctypes.c_void_p), ("nb_idx", ctypes.c_void_p),
+        ("nb_dist", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -165,6 +167,15 @@ def _marshal(spec, keep: list) -> Spec:
     s.ev_type = _ptr(arrays["ev_event"])
     for k in ("time", "node", "dest", "n", "select", "shift", "prop"):
         setattr(s, "ev_" + k, _ptr(arrays["ev_" + k]))
+    nb = getattr(spec, "neighbours", None)
+    if nb is not None:
+        arrays["nb_ptr"] = _c(nb["ptr"], np.int32)
+        arrays["nb_idx"] = _c(nb["idx"], np.int32)
+        arrays["nb_dist"] = _c(nb["dist"], np.float64)
+        s.Nnb = arrays["nb_idx"].size
+        s.nb_ptr = _ptr(arrays["nb_ptr"])
+        s.nb_idx = _ptr(arrays["nb_idx"])
+        s.nb_dist = _ptr(arrays["nb_dist"])
     return s
 
 

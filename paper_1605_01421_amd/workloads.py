@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SIR, SIS, SISE, BIRTH_DEATH, IMMIGRATION_DEATH = 0, 1, 2, 3, 4
+SIR, SIS, SISE, BIRTH_DEATH, IMMIGRATION_DEATH, SISE_SP = 0, 1, 2, 3, 4, 5
 EXIT, ENTER, INTTRANS, EXTTRANS = 0, 1, 2, 3
 EVENT_FIELDS = ("event", "time", "node", "dest", "n", "proportion", "select", "shift")
 
@@ -66,6 +66,9 @@ class ModelSpec:
     N: np.ndarray
     events: dict = field(default_factory=empty_events)
     name: str = ""
+    # SISe_sp: the sparse distance matrix of section 4.2 in compressed
+    # columns, dict(ptr (Nn+1,), idx (nnz,), dist (nnz,)); None otherwise
+    neighbours: dict = None
 
     @property
     def Nn(self) -> int:
@@ -153,6 +156,78 @@ def sise_spec(u0, tspan, upsilon, gamma, alpha, beta_q, end_q=(91, 182, 273, 365
     gd = np.array([upsilon, gamma, alpha, *beta_q], dtype=np.float64)
     return ModelSpec(SISE, S, G, u0, v0, ld, gd, np.asarray(tspan, dtype=np.float64),
                      E, N, events if events is not None else empty_events(), name)
+
+
+def distance_matrix(x, y, cutoff):
+    """The neighbours of each node within `cutoff` (Euclidean, same units as
+    x, y) and their distances, as compressed columns dict(ptr, idx, dist):
+    node i's neighbours, in increasing index, are idx[ptr[i]:ptr[i+1]] (the
+    node itself excluded).  Found through a grid of cells of side cutoff."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(x)
+    cx = np.floor(x / cutoff).astype(np.int64)
+    cy = np.floor(y / cutoff).astype(np.int64)
+    cells = {}
+    for i in range(n):
+        cells.setdefault((int(cx[i]), int(cy[i])), []).append(i)
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    idx, dist = [], []
+    for i in range(n):
+        cand = []
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                cand.extend(cells.get((int(cx[i]) + dx, int(cy[i]) + dy), ()))
+        cand = np.array(sorted(c for c in cand if c != i), dtype=np.int64)
+        if cand.size:
+            d = np.hypot(x[cand] - x[i], y[cand] - y[i])
+            keep = d <= cutoff
+            idx.append(cand[keep])
+            dist.append(d[keep])
+            ptr[i + 1] = ptr[i] + int(keep.sum())
+        else:
+            ptr[i + 1] = ptr[i]
+    return dict(ptr=ptr.astype(np.int32),
+                idx=(np.concatenate(idx) if idx else np.zeros(0)).astype(np.int32),
+                dist=(np.concatenate(dist) if dist else np.zeros(0)).astype(np.float64))
+
+
+def sise_sp_spec(u0, tspan, upsilon, gamma, alpha, beta_q, coupling, neighbours, end_q=(91, 182, 273, 365),
+                 phi0=0.0, events=None, name="SISe_sp") -> ModelSpec:
+    """SISe_sp (section 4.2): SISe with the spatial coupling of the
+    environmental pressure among proximal nodes; gdata = (upsilon, gamma,
+    alpha, beta_1..beta_4, coupling D), `neighbours` the sparse distance
+    matrix (distance_matrix)."""
+    spec = sise_spec(u0, tspan, upsilon, gamma, alpha, beta_q, end_q, phi0, events, name)
+    spec.model = SISE_SP
+    spec.gdata = np.append(spec.gdata, float(coupling))
+    spec.neighbours = neighbours
+    return spec
+
+
+def sise_sp_with_events(seed: int = 6, Nn: int = 1600, days: int = 1460, density_per_km2: float = 0.64,
+                        cutoff_m: float = 2500.0, upsilon=0.012, gamma=0.1, alpha=1.0,
+                        beta_q=(0.10, 0.12, 0.12, 0.10), coupling=0.2, events=True) -> ModelSpec:
+    """The SISe_sp example of section 4.2 on synthetic farms: Nn farms placed
+    uniformly at random in a square whose side gives `density_per_km2`
+    farms per km^2 (1600 farms in 50 x 50 km by default), neighbours within
+    2500 m, 10% of the farms with 5% of their animals infected, phi0 = 0,
+    the example's parameters (upsilon 0.012, gamma 0.1, alpha 1, beta
+    0.10/0.12/0.12/0.10, coupling 0.2), herd sizes and scheduled events as in
+    sise_with_events (births, exits and movements)."""
+    rng = np.random.default_rng(seed)
+    side_m = np.sqrt(Nn / density_per_km2) * 1000.0
+    xs, ys = rng.uniform(0.0, side_m, Nn), rng.uniform(0.0, side_m, Nn)
+    nb = distance_matrix(xs, ys, cutoff_m)
+    size = np.maximum(np.round(rng.lognormal(np.log(40.0), 0.39, Nn)), 1).astype(np.int64)
+    I0 = np.zeros(Nn, np.int64)
+    inf = rng.choice(Nn, size=max(1, Nn // 10), replace=False)
+    I0[inf] = np.floor(0.05 * size[inf]).astype(np.int64)
+    u0 = np.stack([size - I0, I0], axis=1).astype(np.int32)
+    ev = (_demographic_events(rng, Nn, size, days, birth=0.0009, exit_=0.0009, ship_frac=0.005,
+                              select_all=2, birth_select=0) if events else None)
+    return sise_sp_spec(u0, np.arange(0, days + 1), upsilon, gamma, alpha, beta_q, coupling, nb, events=ev,
+                        name=f"sise-sp-{Nn}x{days}")
 
 
 def birth_death_spec(x0, tspan, b, d, immigration=False, name=None) -> ModelSpec:
