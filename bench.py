@@ -93,7 +93,7 @@ def measured_traffic_at(kernel: str, workload: str):
         return None, None
 
 
-MODEL_NAMES = {0: "SIR", 1: "SIS", 2: "SISe", 3: "birth-death", 4: "immigration-death"}
+MODEL_NAMES = {0: "SIR", 1: "SIS", 2: "SISe", 3: "birth-death", 4: "immigration-death", 5: "SISe_sp"}
 HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E (published)
 
 
@@ -103,7 +103,8 @@ def algorithmic_bytes(spec, record_sums: bool) -> float:
     local event records (16 B) read once, each external transfer's two
     per-node items and records (2 x 32 B), and the records written: per node
     and record 4 B per compartment and 8 B per continuous variable, or, for a
-    batch recorded as sums, 8 B per run, record and compartment."""
+    batch recorded as sums, 8 B per run, record and compartment; for a
+    spatially coupled model each stored neighbour's index and weight once."""
     runs = spec if isinstance(spec, list) else [(spec, 1)]
     total = 0.0
     for sp, reps in runs:
@@ -116,6 +117,10 @@ def algorithmic_bytes(spec, record_sums: bool) -> float:
         ntspan = int(np.asarray(sp.tspan).size)
         per_run = nn * (4 * nc + 8 * (nv + nld) + 12) + 16 * n_e1 + 64 * n_e2
         per_run += 8 * ntspan * nc if record_sums else ntspan * nn * (4 * nc + 8 * nv)
+        if getattr(sp, "neighbours", None) is not None:
+            # the coupled post-time step: each neighbour's index and weight
+            # read once (4 B + 8 B); the daily posts stay in the caches
+            per_run += 12 * len(sp.neighbours["idx"])
         total += reps * per_run
     return float(total)
 
@@ -130,6 +135,8 @@ def build_workload(name):
         spec = W.plain_sir()
     elif name == "sise-events":
         spec = W.sise_with_events()
+    elif name == "sise-sp":
+        spec = W.sise_sp_with_events()
     elif name == "ensemble":
         sets = W.ensemble_sets(seed=3, n_sets=64, replicates=64)
         nodes = sum(s.spec.Nn for s in sets) * 64
@@ -263,7 +270,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ensemble",
-                    help="ensemble (default: 64 sets x 64 replicates), sir-events, sise-events, sir-plain, mlp")
+                    help="ensemble (default: 64 sets x 64 replicates), sir-events, sise-events, sise-sp, sir-plain, mlp")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per node: 0 auto, 1, 64")

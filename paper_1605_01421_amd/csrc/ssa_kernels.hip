@@ -321,6 +321,21 @@ template <class M>
 __device__ __forceinline__ int ssa_lattice(const KParams& p, Node<M>& s, double t, double T, uint32_t day_word,
                                            uint32_t node, uint32_t stream, unsigned long long& transitions,
                                            unsigned long long& draws) {
+    {
+        // the day's first state, checked as the walk's first pass would (a
+        // node whose rates are all zero costs no draw)
+        bool neg = false;
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) neg |= s.u[c] < 0;
+        if (neg) return E_NEG_STATE;
+        const double w0 = M::template rate<0>(s.u, s.v, s.ld, s.gd);
+        const double w1 = M::template rate<1>(s.u, s.v, s.ld, s.gd);
+        if (!rate_ok(w0) || !rate_ok(w1)) return E_BAD_RATE;
+        double lam = 0.0;
+        lam = lam + w0;
+        lam = lam + w1;
+        if (!(lam > 0.0)) return 0;
+    }
     const int lane = threadIdx.x & (WAVE - 1);
     int lk = 0;
     while ((lk + 1) * (lk + 2) / 2 <= lane) ++lk;
@@ -731,10 +746,26 @@ struct Tally {
     unsigned long long tr = 0, nd = 0, ev = 0, dr = 0;
 };
 
+// The node-local event records ahead of a wavefront-wide node: lane j holds
+// record from + j (the last one repeated past the node's end), so that its
+// events cost one memory round trip per WAVE records rather than one each.
+// Requires from < cend.
+__device__ __forceinline__ int4 e1_window(const KParams& p, int from, int cend) {
+    return p.e1.rec[min(from + (int)(threadIdx.x & (WAVE - 1)), cend - 1)];
+}
+
+__device__ __forceinline__ int4 read_lane4(int4 v, int lane) {
+    return make_int4(__builtin_amdgcn_readlane(v.x, lane), __builtin_amdgcn_readlane(v.y, lane),
+                     __builtin_amdgcn_readlane(v.z, lane), __builtin_amdgcn_readlane(v.w, lane));
+}
+
 // Loads node k's constant data and initial state (registers for the run).
+// nrec: the record at cur, or, for a wavefront-wide node, the window of
+// records from wbase = cur.
 template <class M>
 __device__ __forceinline__ void load_node(const KParams& p, int k, Node<M>& s, int& run, uint32_t& node,
-                                          uint32_t& stream, int64_t& ord, int& cur, int& cend, int4& nrec) {
+                                          uint32_t& stream, int64_t& ord, int& cur, int& cend, int4& nrec,
+                                          bool wide, int& wbase) {
     load_static<M>(p, s, k, run);
 #pragma unroll
     for (int c = 0; c < M::NC; ++c) s.u[c] = p.u0[(size_t)c * p.n + k];
@@ -745,18 +776,22 @@ __device__ __forceinline__ void load_node(const KParams& p, int k, Node<M>& s, i
     ord = p.node_ord[k];
     cur = p.e1_off[k];
     cend = p.e1_off[k + 1];
-    if (cur < cend) nrec = p.e1.rec[cur];
+    wbase = cur;
+    if (cur < cend) nrec = wide ? e1_window(p, cur, cend) : p.e1.rec[cur];
 }
 
 // The node-local events of the day (time <= T), in key order (section 3.3:
 // exit, enter, internal transfer).  `counter`: the lane that counts them.
 // nrec holds the record at cur, loaded ahead so that days without events
-// wait for no memory access.
-template <class M>
+// wait for no memory access; for a wavefront-wide node (WIDE, cur and
+// wbase wave-uniform) the window of records from wbase (e1_window).
+template <class M, bool WIDE>
 __device__ __forceinline__ void day_events(const KParams& p, Node<M>& s, int b, double T, uint32_t stream, int& cur,
-                                           int cend, int4& nrec, bool& dead, Tally& t, bool counter) {
-    while (cur < cend && (double)nrec.x <= T) {
-        const int rc = apply_event<M::NC>(nrec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
+                                           int cend, int4& nrec, int& wbase, bool& dead, Tally& t, bool counter) {
+    while (cur < cend) {
+        const int4 rec = WIDE ? read_lane4(nrec, cur - wbase) : nrec;
+        if (!((double)rec.x <= T)) break;
+        const int rc = apply_event<M::NC>(rec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
         if (rc) {
             raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
             dead = true;
@@ -764,7 +799,14 @@ __device__ __forceinline__ void day_events(const KParams& p, Node<M>& s, int b, 
         }
         t.ev += counter ? 1 : 0;
         ++cur;
-        if (cur < cend) nrec = p.e1.rec[cur];
+        if (cur < cend) {
+            if constexpr (!WIDE) {
+                nrec = p.e1.rec[cur];
+            } else if (cur - wbase >= WAVE) {
+                wbase = cur;
+                nrec = e1_window(p, cur, cend);
+            }
+        }
     }
 }
 
@@ -783,7 +825,8 @@ __device__ __forceinline__ void group_day(const KParams& p, Node<M>& s, bool liv
         dead = true;
         return;
     }
-    day_events<M>(p, s, b, T, stream, cur, cend, nrec, dead, t, counter);
+    int wbase = cur;
+    day_events<M, false>(p, s, b, T, stream, cur, cend, nrec, wbase, dead, t, counter);
 }
 
 // SSA to day boundary b, then the node's E1 events with time <= T.  With
@@ -792,7 +835,7 @@ __device__ __forceinline__ void group_day(const KParams& p, Node<M>& s, bool liv
 // lane 0 only.
 template <class M, bool PIPE>
 __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, int64_t day, uint32_t node,
-                                           uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec,
+                                           uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec, int& wbase,
                                            bool& dead, Tally& t, bool wide) {
     const double T = (double)day;
     const double t0 = b == 0 ? p.t0 : T - 1.0;
@@ -805,7 +848,11 @@ __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, 
         dead = true;
         return;
     }
-    day_events<M>(p, s, b, T, stream, cur, cend, nrec, dead, t, !wide || (threadIdx.x & (WAVE - 1)) == 0);
+    // (the branch is uniform: a wavefront carries one wide node or none)
+    if (wide)
+        day_events<M, true>(p, s, b, T, stream, cur, cend, nrec, wbase, dead, t, (threadIdx.x & (WAVE - 1)) == 0);
+    else
+        day_events<M, false>(p, s, b, T, stream, cur, cend, nrec, wbase, dead, t, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -838,7 +885,9 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
         uint32_t node = 0, stream = 0;
         int64_t ord = 0;
         int4 nrec = make_int4(0, 0, 0, 0);
-        if (active) load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec);
+        int wbase = 0;
+        if (active) load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec, wide, wbase);
+
         bool dead = false;
         uint64_t key_raw = 0;  // error key, refreshed every 8 days and read 8 days later
         for (int b = 0; b < p.nb; ++b) {
@@ -850,7 +899,7 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
             const int64_t day = p.T1 + b;
             if (grp) group_day<M>(p, s, active && !dead, b, day, node, stream, ord, cur, cend, nrec, dead, t, owner);
             if (active && !dead) {
-                if (!grp) ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
+                if (!grp) ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, wbase, dead, t, wide);
                 if (!dead && !M::pts(s.v, s.u, s.ld, s.gd, day)) {
                     if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
                     dead = true;
@@ -1237,20 +1286,24 @@ __device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long
 
 // The coupling sum of a spatially coupled post-time step (SISe_sp): every
 // node posts its continuous state before the step and its size after the
-// day's events, then adds up the coupling terms of its neighbours' posts in
-// stored order, waiting for each post.  Every node posts before it waits,
+// day's events, waits for the day's posts of its neighbours, then adds up
+// their coupling terms in stored order.  Every node posts before it waits,
 // so every wait ends (all node wavefronts are resident in this kernel).
 // Posts alternate between two buffers by day parity.  A node also waits for
 // the day's posts of the nodes that read it (whether or not it reads them,
 // and whatever its size): it can then overwrite a buffer two days on only
 // after every reader has posted the next day, that is, has finished reading
-// the post it overwrites.
+// the post it overwrites.  The wait looks at CPL_PEEK posts at once, so that
+// their round trips to memory overlap; one acquire fence then covers every
+// post read.
 // Called by every lane of the wavefront (the wait loop is wave-uniform);
 // `active` lanes carry a node, `owner` is the lane that posts for it, and
 // nodes that an error stopped keep posting their last state.  c is 0 for an
 // empty node.  A wait longer than the wall-clock limit abandons the run; an
 // earlier error lets the waits give up (the run's later results are
 // undefined).
+constexpr int CPL_PEEK = 8;
+
 template <class M>
 __device__ __forceinline__ double coupled_sum(const KParams& p, const Node<M>& s, int k, int b, bool active,
                                               bool owner) {
@@ -1261,26 +1314,27 @@ __device__ __forceinline__ double coupled_sum(const KParams& p, const Node<M>& s
         post[k].n = ni;
         __hip_atomic_store(&post[k].day, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    double c = 0.0;
-    int e = active ? p.cpl_off[k] : 0;
+    const int e0 = active ? p.cpl_off[k] : 0;
     const int eend = active ? p.cpl_off[k + 1] : 0;
-    const int fend = active && ni > 0 ? p.cpl_fend[k] : e;
+    int e = e0;
     unsigned spins = 0;
     WaitClock clock;
     while (__any(e < eend)) {
-        bool moved = false;
-        if (e < eend) {
-            const int j = p.cpl_idx[e];
-            if (__hip_atomic_load(&post[j].day, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == b) {
-                if (e < fend) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    c = c + M::coupling_term(post[j].phi, post[j].n, s.v[0], ni, p.cpl_w[e]);
-                }
-                ++e;
-                moved = true;
-            }
+        int32_t d[CPL_PEEK];
+#pragma unroll
+        for (int q = 0; q < CPL_PEEK; ++q)
+            d[q] = e + q < eend
+                       ? __hip_atomic_load(&post[p.cpl_idx[e + q]].day, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : b;
+        int ready = 0;
+        bool gap = false;
+#pragma unroll
+        for (int q = 0; q < CPL_PEEK; ++q) {
+            gap = gap || d[q] != b;
+            ready += gap ? 0 : 1;
         }
-        if (!__any(moved) && (++spins & 255u) == 0) {
+        e = min(e + ready, eend);
+        if (!__any(ready > 0) && (++spins & 255u) == 0) {
             const bool quit = __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                               load_error_step(p.ctrl) < (uint64_t)b;
             const bool late = __shfl(clock.expired(p.wait_ticks) ? 1 : 0, 0, WAVE) != 0;
@@ -1288,6 +1342,16 @@ __device__ __forceinline__ double coupled_sum(const KParams& p, const Node<M>& s
                 __hip_atomic_store(&p.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (__any(quit) || late) break;
             __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double c = 0.0;
+    if (active && ni > 0) {
+        const int fend = p.cpl_fend[k];
+#pragma unroll 4
+        for (int f = e0; f < fend; ++f) {
+            const int j = p.cpl_idx[f];
+            c = c + M::coupling_term(post[j].phi, post[j].n, s.v[0], ni, p.cpl_w[f]);
         }
     }
     return c;
@@ -1319,14 +1383,16 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     uint32_t node = 0, stream = 0;
     int64_t ord = 0;
     int4 nrec = make_int4(0, 0, 0, 0), item = make_int4(0, INT_MAX, 0, 0), trec = make_int4(0, 0, 0, 0);
+    int wbase = 0;
     if (active) {
-        load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec);
+        load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec, wide, wbase);
         tcur = p.e2n_off[k];
         tend = p.e2n_off[k + 1];
         if (tcur < tend) {
             item = p.e2n_item[tcur];
             trec = p.e2n_rec[tcur];
         }
+
     }
     bool dead = false;
     uint64_t key_raw = 0;  // error key, refreshed every 8 days and read 8 days later
@@ -1340,7 +1406,7 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
         if (grp)
             group_day<M>(p, s, active && !dead, b, day, node, stream, ord, cur, cend, nrec, dead, t, owner);
         else if (active && !dead)
-            ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, dead, t, wide);
+            ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, wbase, dead, t, wide);
 
         // this step's external transfers of the node, in key order.  The loop
         // is uniform over the wavefront and every lane that can move on does:
@@ -1488,8 +1554,9 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams pa) {
                 int cur = p.e1_cur[k];
                 const int cend = p.e1_off[k + 1];
                 int4 nrec = cur < cend ? p.e1.rec[cur] : make_int4(0, 0, 0, 0);
-                ssa_and_e1<M, PIPE>(p, s, b, day, (uint32_t)p.node_idx[k], stream, ord, cur, cend, nrec, dead, t,
-                                    false);
+                int wbase = cur;
+                ssa_and_e1<M, PIPE>(p, s, b, day, (uint32_t)p.node_idx[k], stream, ord, cur, cend, nrec, wbase, dead,
+                                    t, false);
                 p.e1_cur[k] = cur;
                 if (!e2day && !dead && !M::pts(s.v, s.u, s.ld, s.gd, day))
                     raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);

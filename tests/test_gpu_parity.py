@@ -605,3 +605,43 @@ def test_lane_queue_graph_replays(lib):
         plain.run(seed, 2)
         assert plain.wait() == 0
         assert np.array_equal(g.sums(), plain.sums()), seed
+
+
+@pytest.mark.parametrize("transfers", [True, False])
+@pytest.mark.parametrize("opts", [dict(lanes=64, wide=3), dict(lanes=64, wide=3, block=256, pipeline=2),
+                                  dict(lanes=64, wide=3, lattice=2)])
+def test_wide_node_event_windows(lib, opts, transfers):
+    """Wavefront-wide nodes read their event records 64 at a time: three
+    heavy nodes with hundreds of events, 150 of them on one day (the window
+    is refilled in the middle of a day), exits of fixed counts and of
+    proportions, births, and (dataflow kernel) transfers to the light nodes
+    or (free-running kernel) none, against the oracle."""
+    rng = np.random.default_rng(17)
+    Nn, days = 40, 30
+    u0 = np.stack([rng.integers(20, 60, Nn), rng.integers(0, 3, Nn), np.zeros(Nn, np.int64)], 1)
+    u0[:3] = [[6000, 40, 0], [5000, 25, 0], [4000, 10, 0]]
+    rows = []
+    for node in range(3):
+        for day in range(1, days + 1):
+            per_day = 150 if day == 7 else int(rng.integers(0, 12))
+            for _ in range(per_day):
+                kind = int(rng.integers(0, 4))
+                if kind == 0:
+                    rows.append((W.EXIT, day, node, 0, int(rng.integers(1, 6)), 0.0, 3, -1))
+                elif kind == 1:
+                    rows.append((W.ENTER, day, node, 0, int(rng.integers(1, 6)), 0.0, 0, -1))
+                elif kind == 2:
+                    rows.append((W.EXIT, day, node, 0, 0, 0.002, 3, -1))
+                else:
+                    rows.append((W.EXTTRANS, day, node, int(rng.integers(3, Nn)), int(rng.integers(1, 4)), 0.0, 3, -1))
+    if not transfers:
+        rows = [r for r in rows if r[0] != W.EXTTRANS]
+    rows.sort(key=lambda r: (r[1], r[0] == W.EXTTRANS))
+    spec = W.sir_spec(u0, np.arange(0, days + 1), 0.3, 0.1, events=W.make_events(rows))
+    m, ref, rc = _run_both(lib, spec, 4, 2, **opts)
+    assert m.launch_info()["mode"] == (2 if transfers else 0)
+    assert rc == 0 and ref["status"] == 0, (rc, ref["status"])
+    assert m.launch_info()["wide"] == 3
+    _compare(m, ref, what=f"event windows {opts}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
