@@ -100,6 +100,59 @@ enum {
     SIMINF_SISE_SP = 5
 };
 
+/* ---- generated models (section 5.1, the model parser) ----------------------
+ * A model given as transition strings "from -> propensity -> to" over named
+ * compartments, global data (gdata), local data (ldata) and continuous state
+ * (v).  `from` and `to` are "@" (the empty set) or terms "X" or "k*X"
+ * (k >= 1) joined by '+'; column j of S is to - from.  The propensity is an
+ * expression in numbers, those names, + - * / (left-associative, * and /
+ * before + and -), unary - and +, and parentheses, evaluated in IEEE
+ * binary64 in the order of its parse tree with every name read as binary64
+ * (compartment counts converted exactly).  G[k][j] (rate k recomputed after
+ * transition j, stored column-major as G[k + j*Nt]) is set when propensity k
+ * reads a compartment that transition j changes.  E and N (select and shift
+ * matrices of the scheduled events, Table 2) are part of the definition:
+ * they are compiled into the model.  The post-time step of a generated model
+ * leaves v unchanged.
+ * siminf_define_model parses the definition, writes S (Nc x Nt) and G
+ * (Nt x Nt) when the pointers are not NULL, and compiles the kernels for it
+ * at run time (hipRTC, gfx950; a few seconds); *model_id is then the value
+ * for siminf_spec.model (the spec's S and G must equal the ones written here,
+ * and a spec with events must carry this E and N).  Returns SIMINF_E_ARG with
+ * the reason in msg (may be NULL) for a definition that does not parse,
+ * SIMINF_E_DEVICE with the compiler's log for a failed compilation, and
+ * SIMINF_E_UNSUPPORTED once SIMINF_GEN_LAST - SIMINF_GEN_FIRST + 1 models
+ * exist in the process.  Definitions are kept until the process ends; a
+ * generated model runs one lane per node (the free-running, barrier and
+ * dataflow kernels; not the lane queue, wavefront-wide nodes or groups). */
+enum {
+    SIMINF_GEN_FIRST = 64,
+    SIMINF_GEN_LAST = 127,
+    SIMINF_GEN_MAX_NC = 16,
+    SIMINF_GEN_MAX_NT = 32
+};
+typedef struct {
+    int32_t nt;                        /* transitions, "from -> propensity -> to" */
+    const char *const *transitions;
+    int32_t nc;                        /* compartment names (the rows of S, E, N) */
+    const char *const *compartments;
+    int32_t ngd;                       /* names of gdata[0..ngd) */
+    const char *const *gdata_names;
+    int32_t nld;                       /* names of ldata[0..nld) of a node */
+    const char *const *ldata_names;
+    int32_t nv;                        /* names of v[0..nv) of a node */
+    const char *const *v_names;
+    int32_t Ecols;                     /* select matrix, nc x Ecols column-major (0/1) */
+    const int32_t *E;
+    int32_t Ncols;                     /* shift matrix, nc x Ncols column-major */
+    const int32_t *N;
+} siminf_model_def;
+int siminf_define_model(const siminf_model_def *def, int32_t *model_id, int32_t *S_out, int32_t *G_out,
+                        char *msg, size_t msg_cap);
+/* The generated source of a model (the model type the kernels were compiled
+ * for); *needed is its length plus one. */
+int siminf_generated_source(int32_t model_id, char *buf, size_t cap, size_t *needed);
+
 /* event type codes (Table 2) */
 enum { SIMINF_EXIT = 0, SIMINF_ENTER = 1, SIMINF_INTTRANS = 2, SIMINF_EXTTRANS = 3 };
 

@@ -60,7 +60,11 @@ class _Model(ctypes.Structure):
         ("ev_shift", ctypes.c_void_p), ("ev_prop", ctypes.c_void_p),
         ("E", ctypes.c_void_p), ("N", ctypes.c_void_p),
         ("Nnb", ctypes.c_int32), ("nb_ptr", ctypes.c_void_p), ("nb_idx", ctypes.c_void_p),
-        ("nb_dist", ctypes.c_void_p)]
+        ("nb_dist", ctypes.c_void_p), ("prog_off", ctypes.c_void_p), ("prog", ctypes.c_void_p),
+        ("consts", ctypes.c_void_p)]
+
+# the model id the C oracle reads as "generated from transition strings"
+MODEL_GENERATED = 64
 
 
 _lib = None
@@ -107,7 +111,15 @@ def run(spec, seed: int, stream: int = 0, nthreads: int | None = None) -> dict:
     lib = load()
     if nthreads is None:
         nthreads = lib.oracle_max_threads()
-    S = np.asarray(spec.S)
+    gen = None
+    if getattr(spec, "mparse", None) is not None:
+        from . import mparse
+        mp = spec.mparse
+        gen = mparse.compile_model(mp["transitions"], mp["compartments"], mp.get("gdata_names", ()),
+                                   mp.get("ldata_names", ()), mp.get("v_names", ()))
+        S, G = gen["S"], gen["G"]
+    else:
+        S, G = np.asarray(spec.S), np.asarray(spec.G)
     Nc, Nt = S.shape
     u0 = _c(spec.u0, np.int32)
     Nn = u0.shape[0]
@@ -115,7 +127,7 @@ def run(spec, seed: int, stream: int = 0, nthreads: int | None = None) -> dict:
     ldata = _c(np.asarray(spec.ldata, dtype=np.float64).reshape(Nn, -1), np.float64)
     keep = dict(
         S=_c(S.ravel(order="F"), np.int32),
-        G=_c(np.asarray(spec.G).ravel(order="F"), np.int32),
+        G=_c(np.asarray(G).ravel(order="F"), np.int32),
         u0=u0, v0=v0, ldata=ldata,
         gdata=_c(spec.gdata, np.float64), tspan=_c(spec.tspan, np.float64),
         E=_c(np.asarray(spec.E).ravel(order="F"), np.int32),
@@ -126,7 +138,13 @@ def run(spec, seed: int, stream: int = 0, nthreads: int | None = None) -> dict:
         keep["ev_" + nm] = _c(ev[nm], np.int32)
     keep["ev_prop"] = _c(ev["proportion"], np.float64)
     m = _Model()
-    m.model = int(spec.model)
+    m.model = MODEL_GENERATED if gen is not None else int(spec.model)
+    if gen is not None:
+        for f in ("prog_off", "prog"):
+            keep[f] = _c(gen[f], np.int32)
+            setattr(m, f, _ptr(keep[f]))
+        keep["consts"] = _c(gen["consts"], np.float64)
+        m.consts = _ptr(keep["consts"])
     m.Nc, m.Nt, m.Nn = Nc, Nt, Nn
     m.Nv, m.Nld = v0.shape[1], ldata.shape[1]
     m.Ngd, m.Ntspan = keep["gdata"].size, keep["tspan"].size

@@ -80,6 +80,9 @@
 #define MODEL_BIRTH_DEATH 3
 #define MODEL_IMMIGRATION_DEATH 4
 #define MODEL_SISE_SP 5
+/* models given as transition strings (section 5.1): ids from 64 on, their
+ * propensities as postfix programs (oracle/mparse.py parses them) */
+#define MODEL_GENERATED_FIRST 64
 
 /* event type codes of Table 2 */
 #define EV_EXIT 0
@@ -106,7 +109,24 @@ typedef struct {
     int32_t Nnb;
     const int32_t *nb_ptr, *nb_idx;
     const double *nb_dist;
+    /* generated models: propensity j is the postfix program
+     * prog[prog_off[j] .. prog_off[j+1]) over the constants consts[] */
+    const int32_t *prog_off, *prog;
+    const double *consts;
 } oracle_model;
+
+/* postfix program operations of a generated model's propensity: the low 8
+ * bits of a program word, the argument (an index) above them */
+#define OP_CONST 0 /* push consts[arg] */
+#define OP_U 1     /* push (double)u[arg] */
+#define OP_GD 2    /* push gd[arg] */
+#define OP_LD 3    /* push ld[arg] */
+#define OP_V 4     /* push v[arg] */
+#define OP_ADD 5
+#define OP_SUB 6
+#define OP_MUL 7
+#define OP_DIV 8
+#define OP_NEG 9
 
 /* ======================================================================
  * Philox4x32-10 (SC'11).  One round maps counter (c0,c1,c2,c3) with key
@@ -298,6 +318,46 @@ static double rate_fn(int model, int j, const int32_t *u, const double *v,
     }
     }
     return NAN;
+}
+
+/* Propensity j of a generated model: its postfix program run on a stack of
+ * binary64 values, one IEEE operation per operator (operands left, then
+ * right).  A malformed program gives NaN, which the caller reports as a bad
+ * rate. */
+static double rate_gen(const oracle_model *m, int j, const int32_t *u, const double *v,
+                       const double *ld, const double *gd) {
+    double st[64];
+    int sp = 0;
+    for (int k = m->prog_off[j]; k < m->prog_off[j + 1]; ++k) {
+        int op = m->prog[k] & 0xff, arg = m->prog[k] >> 8;
+        if (op <= OP_V) {
+            if (sp >= 64)
+                return NAN;
+            st[sp++] = op == OP_CONST ? m->consts[arg]
+                       : op == OP_U   ? (double)u[arg]
+                       : op == OP_GD  ? gd[arg]
+                       : op == OP_LD  ? ld[arg]
+                                      : v[arg];
+        } else if (op == OP_NEG) {
+            if (sp < 1)
+                return NAN;
+            st[sp - 1] = -st[sp - 1];
+        } else {
+            if (sp < 2)
+                return NAN;
+            double a = st[sp - 2], b = st[sp - 1];
+            sp -= 1;
+            st[sp - 1] = op == OP_ADD ? a + b : op == OP_SUB ? a - b : op == OP_MUL ? a * b : a / b;
+        }
+    }
+    return sp == 1 ? st[0] : NAN;
+}
+
+static double rate_any(const oracle_model *m, int j, const int32_t *u, const double *v,
+                       const double *ld, const double *gd) {
+    if (m->model >= MODEL_GENERATED_FIRST)
+        return rate_gen(m, j, u, v, ld, gd);
+    return rate_fn(m->model, j, u, v, ld, gd);
 }
 
 static int model_dims(int model, int *Nc, int *Nt, int *Nv, int *Nld,
@@ -527,7 +587,12 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
     err[0] = 0;
     err[1] = err[2] = err[3] = -1;
     counters[0] = counters[1] = counters[2] = 0;
-    if (!model_dims(m->model, &Nc, &Nt, &Nv, &Nld, &Ngd))
+    if (m->model >= MODEL_GENERATED_FIRST) {
+        /* a generated model has the sizes it was given */
+        if (!m->prog_off || !m->prog || m->Nc < 1 || m->Nt < 1 || m->Nt > 32 || m->Nv > 64)
+            return err[0] = OR_E_ARG;
+        Nc = m->Nc; Nt = m->Nt; Nv = m->Nv; Nld = m->Nld; Ngd = m->Ngd;
+    } else if (!model_dims(m->model, &Nc, &Nt, &Nv, &Nld, &Ngd))
         return err[0] = OR_E_UNSUPPORTED;
     if (m->Nc != Nc || m->Nt != Nt || m->Nv != Nv || m->Nld < Nld ||
         m->Ngd < Ngd || m->Nn < 0 || m->Ntspan < 1 || m->Nev < 0)
@@ -646,7 +711,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
             node_err[i] = NOERR;
             int bad = 0;
             for (int j = 0; j < Nt; ++j) {
-                w[j] = rate_fn(m->model, j, ui, vi, ld, m->gdata);
+                w[j] = rate_any(m, j, ui, vi, ld, m->gdata);
                 if (!(w[j] >= 0.0) || !isfinite(w[j]))
                     bad = 1;
             }
@@ -705,7 +770,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
                     break;
                 for (int j = 0; j < Nt; ++j) {
                     if (m->G[(size_t)n * Nt + j] != 0) {
-                        w[j] = rate_fn(m->model, j, ui, vi, ld, m->gdata);
+                        w[j] = rate_any(m, j, ui, vi, ld, m->gdata);
                         if (!(w[j] >= 0.0) || !isfinite(w[j]))
                             bad = OR_E_BAD_RATE;
                     }

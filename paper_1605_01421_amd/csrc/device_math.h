@@ -2,8 +2,7 @@
 // SSA kernels.  Device code for gfx950; compiled with -ffp-contract=off so
 // every floating-point operation below is exactly one IEEE binary64 rounding.
 #pragma once
-#include <hip/hip_runtime.h>
-#include <stdint.h>
+#include "device_types.h"
 
 namespace siminf {
 

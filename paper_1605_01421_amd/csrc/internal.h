@@ -1,8 +1,7 @@
 // internal.h -- structures shared by the host runtime (runtime.cpp) and the
 // kernels (ssa_kernels.hip).  Not part of the public ABI.
 #pragma once
-#include <hip/hip_runtime.h>
-#include <stdint.h>
+#include "device_types.h"
 
 namespace siminf {
 
@@ -151,7 +150,7 @@ struct KParams {
     const int4* e2n_item;        //           x = event index, y = step, z = role (0 source,
                                  //           1 destination, 2 both), w = run of the event
     unsigned long long* mail;    // dataflow: [n_e2] counts a transfer delivers (0 = not yet)
-    int32_t* mail_big;           //           [n_e2][MAX_NC] counts too large to pack
+    int32_t* mail_big;           //           [n_e2][Nc] counts too large to pack
     int32_t n_e2;
     int32_t record;              // 0 full, 1 sums
     int32_t sums_nc;             // compartment stride of the sums array
@@ -193,6 +192,7 @@ constexpr int LQ_SLOTS = 2;
 constexpr int LQ_LDS_BYTES = 64 * 1024;
 
 // Launchers implemented in ssa_kernels.hip.
+#ifndef __HIPCC_RTC__
 hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st);
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem,
@@ -201,8 +201,12 @@ int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, si
                       bool lane_queue = false);
 hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nmajor,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
+// generated models (generated.cpp): launch through the run-time compiled module
+hipError_t generated_launch(int id, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st);
+int generated_blocks_per_cu(int id, int mode, int pipeline, int block, size_t shmem);
 hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,
                              int case_c, uint32_t mask, int reps, int k0, int nk,
                              const double* probs, int nq, float* out, hipStream_t st);
+#endif  // __HIPCC_RTC__
 
 }  // namespace siminf

@@ -5,8 +5,7 @@
 // the results must be bit-identical to any other implementation following
 // the same formulas in IEEE binary64.
 #pragma once
-#include <hip/hip_runtime.h>
-#include <stdint.h>
+#include "device_types.h"
 
 namespace siminf {
 
@@ -18,7 +17,7 @@ __device__ __forceinline__ double pick(bool c, double a, double b) { return c ? 
 // (Appendix C listing); I -> R at gamma I.  gdata = (beta, gamma).
 struct ModelSIR {
     static constexpr int ID = M_SIR, NC = 3, NT = 2, NV = 0, NLD = 0, NGD = 2;
-    static constexpr bool COUPLED = false;
+    static constexpr bool COUPLED = false, GENERATED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -41,7 +40,7 @@ struct ModelSIR {
 // SIS (eqs. sirtrans, SIRstoich): S + I -> 2I at beta S I; I -> S at gamma I.
 struct ModelSIS {
     static constexpr int ID = M_SIS, NC = 2, NT = 2, NV = 0, NLD = 0, NGD = 2;
-    static constexpr bool COUPLED = false;
+    static constexpr bool COUPLED = false, GENERATED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -68,7 +67,7 @@ struct ModelSIS {
 // gdata = (upsilon, gamma, alpha, beta_1, beta_2, beta_3, beta_4).
 struct ModelSISe {
     static constexpr int ID = M_SISE, NC = 2, NT = 2, NV = 1, NLD = 4, NGD = 7;
-    static constexpr bool COUPLED = false;
+    static constexpr bool COUPLED = false, GENERATED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double* v, const double*,
                                                   const double* gd) {
@@ -121,7 +120,7 @@ struct ModelSISe {
 // gdata = (upsilon, gamma, alpha, beta_1, beta_2, beta_3, beta_4, D).
 struct ModelSISeSp {
     static constexpr int ID = M_SISE_SP, NC = 2, NT = 2, NV = 1, NLD = 4, NGD = 8;
-    static constexpr bool COUPLED = true;
+    static constexpr bool COUPLED = true, GENERATED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double* v, const double* ld,
                                                   const double* gd) {
@@ -159,7 +158,7 @@ struct ModelSISeSp {
 // Linear birth-death: X -> 2X at b X, X -> 0 at d X.  gdata = (b, d).
 struct ModelBirthDeath {
     static constexpr int ID = M_BIRTH_DEATH, NC = 1, NT = 2, NV = 0, NLD = 0, NGD = 2;
-    static constexpr bool COUPLED = false;
+    static constexpr bool COUPLED = false, GENERATED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {
@@ -176,7 +175,7 @@ struct ModelBirthDeath {
 // Immigration-death: 0 -> X at kappa, X -> 0 at mu X.  gdata = (kappa, mu).
 struct ModelImmigrationDeath {
     static constexpr int ID = M_IMMIGRATION_DEATH, NC = 1, NT = 2, NV = 0, NLD = 0, NGD = 2;
-    static constexpr bool COUPLED = false;
+    static constexpr bool COUPLED = false, GENERATED = false;
     template <int J>
     __device__ static __forceinline__ double rate(const int32_t* u, const double*, const double*,
                                                   const double* gd) {

@@ -20,7 +20,17 @@
 
 using namespace siminf;
 
+namespace siminf {
+// generated models (generated.cpp)
+bool generated_shape(int id, ModelShape* s);
+int generated_check_spec(const siminf_spec& s);
+}  // namespace siminf
+
 namespace {
+
+bool is_generated(int model) { return model >= SIMINF_GEN_FIRST && model <= SIMINF_GEN_LAST; }
+
+bool shape_of(int model, ModelShape* s) { return model_shape(model, s) || (is_generated(model) && generated_shape(model, s)); }
 
 struct RunInfo {
     int spec;
@@ -134,7 +144,7 @@ void set_create_error(siminf_model* m, int code, int64_t index, int run) {
 int validate_spec(const siminf_spec& s, int64_t* bad_event) {
     *bad_event = -1;
     ModelShape sh;
-    if (!model_shape(s.model, &sh)) return SIMINF_E_UNSUPPORTED;
+    if (!shape_of(s.model, &sh)) return SIMINF_E_UNSUPPORTED;
     if (s.Nc != sh.nc || s.Nt != sh.nt) return SIMINF_E_ARG;
     if (s.Nv != sh.nv || s.Nld < sh.nld || s.Ngd < sh.ngd) return SIMINF_E_ARG;
     if (s.Nn < 0 || s.Ntspan < 1 || s.Nev < 0 || s.Ecols < 0 || s.Ncols < 0) return SIMINF_E_ARG;
@@ -163,6 +173,11 @@ int validate_spec(const siminf_spec& s, int64_t* bad_event) {
             return SIMINF_E_ARG;
         if (s.Ecols > 0 && !s.E) return SIMINF_E_ARG;
         if (s.Ncols > 0 && !s.N) return SIMINF_E_ARG;
+    }
+    if (is_generated(s.model)) {
+        // S, G and the event tables are the model's own
+        const int rc = generated_check_spec(s);
+        if (rc) return rc;
     }
     for (int e = 0; e < s.Nev; ++e) {
         const int ty = s.ev_type[e];
@@ -266,7 +281,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     KParams& p = g.p;
     p.lane_queue = 0;
     g.lq_chunk = 0;
-    if (lq_chunk > 0 && g.n_e2 == 0 && !p.coupled) {
+    if (lq_chunk > 0 && g.n_e2 == 0 && !p.coupled && !is_generated(g.model)) {
         const int cus = device_cus(m);
         if (cus <= 0) return SIMINF_E_DEVICE;
         if (block == 0) block = 256;
@@ -330,6 +345,11 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         return SIMINF_OK;
     }
     if (lq_chunk > 0) return SIMINF_E_UNSUPPORTED;
+    // a generated model runs one lane per node
+    if (is_generated(g.model)) {
+        nbig = 0;
+        ngrp = 0;
+    }
     // the coupled post-time step: the dataflow kernel only, every node resident
     const bool coupled = p.coupled != 0;
     if (coupled && want_mode == 1) return SIMINF_E_UNSUPPORTED;
@@ -489,16 +509,20 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
     }
 
     // ---- runs and model groups ---------------------------------------------
-    std::vector<int> group_of_model(8, -1);
+    std::vector<int> group_of_model(SIMINF_GEN_LAST + 1, -1);  // built-in and generated model ids
     std::vector<int> group_spec0;
     int64_t noff = 0, eoff = 0;
     for (int s = 0; s < nspecs; ++s) {
         const int model = specs[s].model;
+        if (model < 0 || model > SIMINF_GEN_LAST) {
+            set_create_error(m, SIMINF_E_UNSUPPORTED, -1, -1);
+            return SIMINF_E_UNSUPPORTED;
+        }
         if (group_of_model[model] < 0) {
             group_of_model[model] = (int)m->groups.size();
             Group g;
             g.model = model;
-            model_shape(model, &g.shape);
+            shape_of(model, &g.shape);
             m->groups.push_back(g);
             group_spec0.push_back(s);
         } else {
@@ -847,6 +871,21 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
                 const Ev& x = perm ? list[(*perm)[j]] : list[j];
                 const siminf_spec& s = S_of(x.run);
                 const int sel = s.ev_select[x.e], q = s.ev_shift[x.e];
+                if (is_generated(g.model)) {
+                    // a generated model's tables are compiled in: the word
+                    // names the column of E and the column of N plus one
+                    const int qq = (q >= 0 && s.ev_type[x.e] != SIMINF_ENTER) ? q + 1 : 0;
+                    const uint32_t wd = (uint32_t)s.ev_type[x.e] | ((uint32_t)sel << 2) | ((uint32_t)qq << 12);
+                    rec[j] = make_int4(s.ev_time[x.e], (int32_t)wd, s.ev_n[x.e], x.e);
+                    prop[j] = s.ev_prop[x.e];
+                    ord[j] = m->runs[x.run].eoff + x.e;
+                    if (transfers) {
+                        nd[j] = local(x.run, s.ev_node[x.e]);
+                        ds[j] = local(x.run, s.ev_dest[x.e]);
+                        rn[j] = x.run;
+                    }
+                    continue;
+                }
                 uint32_t mask = 0;
                 int target[MAX_NC] = {0, 1, 2, 3};
                 for (int c = 0; c < nc; ++c) {
@@ -886,14 +925,17 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         p.T1 = m->T1;
         p.t0 = m->t0;
         p.ngd = std::max(ngd_max, 1);
-        for (int j = 0; j < g.shape.nt; ++j) {
+        for (int j = 0; j < (is_generated(g.model) ? 0 : g.shape.nt); ++j) {
             for (int c = 0; c < nc; ++c) p.S[c + j * nc] = sp.S[c + (size_t)j * nc];
             uint32_t mask = 0;
             for (int k = 0; k < g.shape.nt; ++k)
                 if (sp.G[k + (size_t)j * g.shape.nt]) mask |= 1u << k;
             p.Gmask[j] = mask;
         }
-        p.lattice = m->opt.lattice != 2 && g.shape.nt == 2 && p.Gmask[0] == 3u && p.Gmask[1] == 3u ? 1 : 0;
+        p.lattice = !is_generated(g.model) && m->opt.lattice != 2 && g.shape.nt == 2 && p.Gmask[0] == 3u &&
+                            p.Gmask[1] == 3u
+                        ? 1
+                        : 0;
         int32_t *d_u0, *d_nrun, *d_nidx, *d_e1off, *d_e2step, *d_e2lvl, *d_e2noff;
         double *d_v0, *d_ld;
         int64_t* d_nord;
@@ -954,12 +996,12 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
             // live state for the transfer kernels (both variants)
             if (alloc_device(m->owned, (size_t)nc * n, &p.u) || alloc_device(m->owned, (size_t)std::max(nv, 1) * n, &p.v) ||
                 alloc_device(m->owned, (size_t)n, &p.e1_cur) || alloc_device(m->owned, (size_t)p.n_e2, &p.mail) ||
-                alloc_device(m->owned, (size_t)p.n_e2 * MAX_NC, &p.mail_big))
+                alloc_device(m->owned, (size_t)p.n_e2 * nc, &p.mail_big))
                 return hip_fail(m);
         }
         g.node_run = node_run;
         int lq = 0;
-        if (g.n_e2 == 0 && !coupled) {
+        if (g.n_e2 == 0 && !coupled && !is_generated(g.model)) {
             // the lane-queue chunk table: at most one chunk per run and per 64 nodes more
             g.chunk_cap = (int)grp_runs.size() + n / 64 + 1;
             if (alloc_device(m->owned, (size_t)g.chunk_cap, &g.d_chunks)) return hip_fail(m);
@@ -1347,7 +1389,7 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     // the lane queue (models without external transfers), at three block
     // sizes and two chunk sizes, unless an option fixes the lane layout
     bool free_only = true;
-    for (const Group& g : m->groups) free_only = free_only && g.n_e2 == 0 && !g.p.coupled;
+    for (const Group& g : m->groups) free_only = free_only && g.n_e2 == 0 && !g.p.coupled && !is_generated(g.model);
     const bool shaped = m->opt.lanes != 0 || m->opt.wide != 0 || m->opt.group != 0 || m->opt.pack != 0;
     if (free_only && m->opt.lane_queue != 2 && (m->opt.lane_queue == 1 || !shaped)) {
         const int ch = m->opt.chunk > 0 ? m->opt.chunk : 512;

@@ -19,18 +19,25 @@
 // The flow and sync kernels are launched cooperatively (all workgroups
 // resident).  Every wait has a wall-clock limit that turns a stall into an
 // error.
+// The device part (everything up to the host launchers) is also compiled at
+// run time with hipRTC for models generated from transition strings; the
+// host part is left out there.
 #include "device_math.h"
 #include "internal.h"
 #include "models.h"
 
+#ifndef __HIPCC_RTC__
 #include <algorithm>
-#include <climits>
+
+#include "siminf.h"
+#endif
 
 namespace siminf {
 
 namespace {
 
 constexpr int E_NEG_STATE = -5, E_BAD_RATE = -6, E_OVERDRAW = -7, E_PTS = -9, E_STEP_LIMIT = -10;
+constexpr int NO_STEP = 0x7fffffff;  // the day index of "no transfer item left"
 constexpr int EV_EXIT = 0, EV_ENTER = 1, EV_EXTTRANS = 3;
 
 // Implementation limit on the draws of one node within one unit of time (the
@@ -82,7 +89,7 @@ struct Node {
     int32_t u[M::NC];
     double v[M::NV > 0 ? M::NV : 1];
     double ld[M::NLD > 0 ? M::NLD : 1];
-    double gd[M::NGD];
+    double gd[M::NGD > 0 ? M::NGD : 1];
 };
 
 __device__ __forceinline__ bool rate_ok(double w) { return w >= 0.0 && isfinite(w); }
@@ -135,6 +142,67 @@ __device__ __forceinline__ Transition<M> transition(const KParams& p, const Node
     return transition_of<M>(p, s.u, s.v, s.ld, s.gd, w0, w1, x);
 }
 
+// Direct-method SSA of a node of a generated model (any number of
+// transitions; state changes, dependency graph and rates compiled into the
+// model type).  The same steps as ssa_to_boundary in the same order, over
+// NT rates: lambda as a left-to-right sum, the step limit before each draw,
+// tau = -log(r1)/lambda, stop if t + tau >= T, inversion (the first
+// transition with a positive rate whose running sum reaches lambda*r2, else
+// the last with a positive rate), the transition's column of S, the
+// negative-state check, and the rates its column of G marks.
+template <class M>
+__device__ __forceinline__ int ssa_generated(const KParams& p, Node<M>& s, double t, double T, uint32_t day_word,
+                                             uint32_t node, uint32_t stream, unsigned long long& transitions,
+                                             unsigned long long& draws) {
+    double w[M::NT];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < M::NT; ++j) {
+        w[j] = M::rate(j, s.u, s.v, s.ld, s.gd);
+        bad = bad || !rate_ok(w[j]);
+    }
+    if (bad) return E_BAD_RATE;
+    const uint32_t k0 = (uint32_t)p.seed, k1 = (uint32_t)(p.seed >> 32);
+    const uint32_t tag = stream & 0xFFFFFFu;
+    for (uint32_t step = 0;; ++step) {
+        double lam = 0.0;
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j) lam = lam + w[j];
+        if (!(lam > 0.0)) return 0;
+        if (step == STEP_LIMIT) return E_STEP_LIMIT;
+        const StepRandoms r = step_randoms(k0, k1, step, day_word, node, tag);
+        draws += 1;
+        const double tn = t + r.e / lam;
+        if (tn >= T) return 0;
+        t = tn;
+        const double x = lam * r.r2;
+        double cum = 0.0;
+        int n = -1, last = -1;
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j) {
+            cum = cum + w[j];
+            const bool pos = w[j] > 0.0;
+            last = pos ? j : last;
+            n = (n < 0 && pos && x <= cum) ? j : n;
+        }
+        if (n < 0) n = last;
+        M::apply(n, s.u);
+        transitions += 1;
+        bool neg = false;
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) neg = neg || s.u[c] < 0;
+        if (neg) return E_NEG_STATE;
+        const uint32_t g = M::deps(n);
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j)
+            if ((g >> j) & 1u) {
+                w[j] = M::rate(j, s.u, s.v, s.ld, s.gd);
+                bad = bad || !rate_ok(w[j]);
+            }
+        if (bad) return E_BAD_RATE;
+    }
+}
+
 // Direct-method SSA of one node from time t to the day boundary T
 // (Appendix A): lambda = w0 + w1, tau = -log(r1)/lambda, stop if
 // t + tau >= T, else pick the transition by inversion with r2, apply its
@@ -145,7 +213,10 @@ template <class M, bool PIPE>
 __device__ __forceinline__ int ssa_to_boundary(const KParams& p, Node<M>& s, double t, double T,
                                                uint32_t day_word, uint32_t node, uint32_t stream,
                                                unsigned long long& transitions, unsigned long long& draws) {
-    static_assert(M::NT == 2, "kernels are written for two-transition models");
+    if constexpr (M::GENERATED) {
+        return ssa_generated<M>(p, s, t, T, day_word, node, stream, transitions, draws);
+    } else {
+    static_assert(M::NT == 2, "the built-in models have two transitions");
     double w0 = M::template rate<0>(s.u, s.v, s.ld, s.gd);
     double w1 = M::template rate<1>(s.u, s.v, s.ld, s.gd);
     if (!rate_ok(w0) || !rate_ok(w1)) return E_BAD_RATE;
@@ -186,6 +257,7 @@ __device__ __forceinline__ int ssa_to_boundary(const KParams& p, Node<M>& s, dou
             cur = step_randoms(k0, k1, step, day_word, node, tag);
     }
     return 0;
+    }
 }
 
 __device__ __forceinline__ double read_lane(double x, int lane) {
@@ -622,15 +694,37 @@ __device__ __forceinline__ int ssa_group(const KParams& p, Node<M>& s, bool live
     return rc;
 }
 
+// The select mask and shift targets of a packed event word: for the
+// built-in models both are in the word (4 mask bits, 2 bits of target per
+// compartment); a generated model's word holds the column of E and the
+// column of N plus one (0: no shift), looked up in the model's tables.
+template <class M>
+__device__ __forceinline__ uint32_t event_mask(uint32_t w) {
+    if constexpr (M::GENERATED)
+        return M::select_mask((int)((w >> 2) & 0x3FFu));
+    else
+        return (w >> 2) & 0xFu;
+}
+template <class M>
+__device__ __forceinline__ int event_target(uint32_t w, int c) {
+    if constexpr (M::GENERATED) {
+        const int q = (int)((w >> 12) & 0x3FFu) - 1;
+        return q < 0 ? c : M::shift_target(q, c);
+    } else {
+        return (int)((w >> (6 + 2 * c)) & 3u);
+    }
+}
+
 // One scheduled event (section 3.3) from its packed record, on node state u
 // (and destination ud for an external transfer).  Indices were validated
 // when the model was created.  Returns 0 or E_OVERDRAW (state unchanged).
-template <int NC>
+template <class M>
 __device__ __forceinline__ int apply_event(const int4 rec, const double* prop, int e, uint64_t seed,
-                                           uint32_t stream, int32_t (&u)[NC], int32_t (&ud)[NC]) {
+                                           uint32_t stream, int32_t (&u)[M::NC], int32_t (&ud)[M::NC]) {
+    constexpr int NC = M::NC;
     const uint32_t w = (uint32_t)rec.y;
     const int type = (int)(w & 3u);
-    const uint32_t mask = (w >> 2) & 0xFu;
+    const uint32_t mask = event_mask<M>(w);
     // every per-compartment update below is an unconditional select so that
     // the state stays in registers (no computed addresses)
     if (type == EV_ENTER) {
@@ -672,7 +766,7 @@ __device__ __forceinline__ int apply_event(const int4 rec, const double* prop, i
     const bool ext = type == EV_EXTTRANS;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const int tgt = (int)((w >> (6 + 2 * c)) & 3u);
+        const int tgt = event_target<M>(w, c);
 #pragma unroll
         for (int d = 0; d < NC; ++d) {
             const int32_t add = (tgt == d) ? take[c] : 0;
@@ -791,7 +885,7 @@ __device__ __forceinline__ void day_events(const KParams& p, Node<M>& s, int b, 
     while (cur < cend) {
         const int4 rec = WIDE ? read_lane4(nrec, cur - wbase) : nrec;
         if (!((double)rec.x <= T)) break;
-        const int rc = apply_event<M::NC>(rec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
+        const int rc = apply_event<M>(rec, p.e1.prop, cur, p.seed, stream, s.u, s.u);
         if (rc) {
             raise_error(p.ctrl, b, PH_E1, p.e1.ordinal[cur], rc);
             dead = true;
@@ -818,7 +912,8 @@ __device__ __forceinline__ void group_day(const KParams& p, Node<M>& s, bool liv
                                           Tally& t, bool counter) {
     const double T = (double)day;
     const double t0 = b == 0 ? p.t0 : T - 1.0;
-    const int rc = ssa_group<M>(p, s, live, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr);
+    int rc = 0;
+    if constexpr (!M::GENERATED) rc = ssa_group<M>(p, s, live, t0, T, (uint32_t)(int32_t)day, node, stream, t.tr, t.dr);
     if (!live) return;
     if (rc) {
         raise_error(p.ctrl, b, PH_SSA, ord, rc);
@@ -840,7 +935,11 @@ __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, 
     const double T = (double)day;
     const double t0 = b == 0 ? p.t0 : T - 1.0;
     const uint32_t dw = (uint32_t)(int32_t)day;
-    int rc = !wide       ? ssa_to_boundary<M, PIPE>(p, s, t0, T, dw, node, stream, t.tr, t.dr)
+    int rc = 0;
+    if constexpr (M::GENERATED)
+        rc = ssa_to_boundary<M, PIPE>(p, s, t0, T, dw, node, stream, t.tr, t.dr);  // never wide
+    else
+        rc = !wide       ? ssa_to_boundary<M, PIPE>(p, s, t0, T, dw, node, stream, t.tr, t.dr)
              : p.lattice ? ssa_lattice<M>(p, s, t0, T, dw, node, stream, t.tr, t.dr)
                          : ssa_wide<M>(p, s, t0, T, dw, node, stream, t.tr, t.dr);
     if (rc) {
@@ -1206,7 +1305,7 @@ __global__ void __launch_bounds__(256) lane_kernel(KParams pa) {
             bool dead = L.fail != 0;
             if (dead) lane_fail<M>(p, L, PH_SSA, p.node_ord[L.k], L.fail, tally);
             while (!dead && L.cur < L.cend && (double)L.etime <= L.T) {
-                const int rc = apply_event<M::NC>(p.e1.rec[L.cur], p.e1.prop, L.cur, seed, L.tag, L.u, L.u);
+                const int rc = apply_event<M>(p.e1.rec[L.cur], p.e1.prop, L.cur, seed, L.tag, L.u, L.u);
                 if (rc) {
                     lane_fail<M>(p, L, PH_E1, p.e1.ordinal[L.cur], rc, tally);
                     dead = true;
@@ -1266,7 +1365,7 @@ __device__ __forceinline__ void post_mail(const KParams& p, int e, const int32_t
         __hip_atomic_store(&p.mail[e], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) p.mail_big[(size_t)e * MAX_NC + c] = cnt[c];
+        for (int c = 0; c < NC; ++c) p.mail_big[(size_t)e * NC + c] = cnt[c];
         __hip_atomic_store(&p.mail[e], MAIL_SIDE, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -1280,7 +1379,7 @@ __device__ __forceinline__ void take_mail(const KParams& p, int e, unsigned long
     } else {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
-        for (int c = 0; c < NC; ++c) u[c] += p.mail_big[(size_t)e * MAX_NC + c];
+        for (int c = 0; c < NC; ++c) u[c] += p.mail_big[(size_t)e * NC + c];
     }
 }
 
@@ -1382,7 +1481,7 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     int run = 0, cur = 0, cend = 0, tcur = 0, tend = 0;
     uint32_t node = 0, stream = 0;
     int64_t ord = 0;
-    int4 nrec = make_int4(0, 0, 0, 0), item = make_int4(0, INT_MAX, 0, 0), trec = make_int4(0, 0, 0, 0);
+    int4 nrec = make_int4(0, 0, 0, 0), item = make_int4(0, NO_STEP, 0, 0), trec = make_int4(0, 0, 0, 0);
     int wbase = 0;
     if (active) {
         load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec, wide, wbase);
@@ -1424,7 +1523,7 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
 #pragma unroll
                     for (int c = 0; c < M::NC; ++c) got[c] = 0;
                     const uint32_t ev_stream = p.stream_base + (uint32_t)item.w;
-                    int rc = dead ? 0 : apply_event<M::NC>(trec, p.e2.prop, e, p.seed, ev_stream, s.u, got);
+                    int rc = dead ? 0 : apply_event<M>(trec, p.e2.prop, e, p.seed, ev_stream, s.u, got);
                     if (rc) {
                         if (owner) raise_error(p.ctrl, b, PH_E2, p.e2.ordinal[e], rc);
                         dead = true;
@@ -1451,7 +1550,7 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
                         item = p.e2n_item[tcur];
                         trec = p.e2n_rec[tcur];
                     } else {
-                        item.y = INT_MAX;
+                        item.y = NO_STEP;
                     }
                 }
                 pending = item.y == b;
@@ -1587,7 +1686,7 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams pa) {
                         before[c] = ud[c];
                     }
                     const uint32_t stream = p.stream_base + (uint32_t)p.e2.run[e];
-                    const int rc = apply_event<M::NC>(p.e2.rec[e], p.e2.prop, e, p.seed, stream, us, ud);
+                    const int rc = apply_event<M>(p.e2.rec[e], p.e2.prop, e, p.seed, stream, us, ud);
                     if (rc) {
                         raise_error(p.ctrl, b, PH_E2, p.e2.ordinal[e], rc);
                     } else {
@@ -1717,6 +1816,7 @@ __global__ void prevalence_kernel(const unsigned long long* sums, int ntspan, in
     }
 }
 
+#ifndef __HIPCC_RTC__
 template <class M, bool PIPE>
 const void* kernel_for(int mode, bool grp) {
     // nodes on groups of lanes have their own instantiations, so that the
@@ -1751,8 +1851,11 @@ const void* model_kernel(int model, int mode, int pipeline, bool grp, bool lq) {
     return nullptr;
 }
 
+#endif  // __HIPCC_RTC__
+
 }  // namespace
 
+#ifndef __HIPCC_RTC__
 hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool reset_ctrl,
                        const unsigned long long* sums_init, long long sums_len, hipStream_t st) {
     int blocks = (int)((std::max(p.coupled ? 2 * p.n : p.n, p.n_e2) + 255) / 256);
@@ -1763,6 +1866,7 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
 }
 
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st) {
+    if (model >= SIMINF_GEN_FIRST) return generated_launch(model, p, block, blocks, shmem, st);
     const void* fn = model_kernel(model, p.mode, p.pipeline, p.ngrp > 0, p.lane_queue != 0);
     if (!fn) return hipErrorInvalidValue;
     KParams arg = p;
@@ -1772,6 +1876,7 @@ hipError_t launch_group(int model, const KParams& p, int block, int blocks, size
 }
 
 int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem, bool lane_queue) {
+    if (model >= SIMINF_GEN_FIRST) return grp || lane_queue ? 0 : generated_blocks_per_cu(model, mode, pipeline, block, shmem);
     const void* fn = model_kernel(model, mode, pipeline, grp, lane_queue);
     int n = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, shmem) != hipSuccess) return 0;
@@ -1794,5 +1899,7 @@ hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspa
     prevalence_kernel<<<sets * nk, 64, shmem, st>>>(sums, ntspan, nc, case_c, mask, reps, k0, nk, probs, nq, out);
     return hipGetLastError();
 }
+
+#endif  // __HIPCC_RTC__
 
 }  // namespace siminf

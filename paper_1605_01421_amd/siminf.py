@@ -58,6 +58,14 @@ class Options(ctypes.Structure):
 
 # exported entry points: name -> (restype, argtypes)
 _P = ctypes.c_void_p
+
+
+class ModelDef(ctypes.Structure):
+    """siminf_model_def: a model given as transition strings (section 5.1)."""
+    _fields_ = [("nt", ctypes.c_int32), ("transitions", _P), ("nc", ctypes.c_int32), ("compartments", _P),
+                ("ngd", ctypes.c_int32), ("gdata_names", _P), ("nld", ctypes.c_int32), ("ldata_names", _P),
+                ("nv", ctypes.c_int32), ("v_names", _P), ("Ecols", ctypes.c_int32), ("E", _P),
+                ("Ncols", ctypes.c_int32), ("N", _P)]
 SIGNATURES = {
     "siminf_create": (ctypes.c_int, [ctypes.POINTER(Spec), ctypes.POINTER(Options), ctypes.POINTER(_P)]),
     "siminf_create_batch": (ctypes.c_int, [ctypes.POINTER(Spec), ctypes.c_int32, _P,
@@ -90,6 +98,10 @@ SIGNATURES = {
     "siminf_mlp_ensemble_predict": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "siminf_mlp_ensemble_predict_static": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P, _P,
                                                           _P]),
+    "siminf_define_model": (ctypes.c_int, [ctypes.POINTER(ModelDef), ctypes.POINTER(ctypes.c_int32), _P, _P,
+                                           ctypes.c_char_p, ctypes.c_size_t]),
+    "siminf_generated_source": (ctypes.c_int, [ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
     "siminf_gemm_bf16": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                         ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                         _P]),
@@ -135,9 +147,66 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
 
 
+_defined: dict = {}
+
+
+def define_model(transitions, compartments, gdata_names=(), ldata_names=(), v_names=(), E=None, N=None) -> dict:
+    """Parses and compiles a model given as transition strings
+    "from -> propensity -> to" (siminf_define_model); returns dict(id, S, G)
+    with S (Nc, Nt) and G (Nt, Nt) as the library derived them.  Definitions
+    are cached per process by their text and tables."""
+    nc, nt = len(compartments), len(transitions)
+    E = np.zeros((nc, 0), np.int32) if E is None else np.asarray(E, dtype=np.int32).reshape(nc, -1)
+    N = np.zeros((nc, 0), np.int32) if N is None else np.asarray(N, dtype=np.int32).reshape(nc, -1)
+    key = (tuple(transitions), tuple(compartments), tuple(gdata_names), tuple(ldata_names), tuple(v_names),
+           E.tobytes(), E.shape, N.tobytes(), N.shape)
+    if key in _defined:
+        return _defined[key]
+    lib = load()
+
+    def strings(xs):
+        arr = (ctypes.c_char_p * max(len(xs), 1))(*[x.encode() for x in xs])
+        return arr, ctypes.cast(arr, _P)
+
+    keep = [strings(list(transitions)), strings(list(compartments)), strings(list(gdata_names)),
+            strings(list(ldata_names)), strings(list(v_names))]
+    Ef = _c(E.ravel(order="F"), np.int32)
+    Nf = _c(N.ravel(order="F"), np.int32)
+    d = ModelDef(nt, keep[0][1], nc, keep[1][1], len(gdata_names), keep[2][1], len(ldata_names), keep[3][1],
+                 len(v_names), keep[4][1], E.shape[1], _ptr(Ef), N.shape[1], _ptr(Nf))
+    mid = ctypes.c_int32(-1)
+    S = np.zeros(nc * nt, np.int32)
+    G = np.zeros(nt * nt, np.int32)
+    msg = ctypes.create_string_buffer(8192)
+    rc = lib.siminf_define_model(ctypes.byref(d), ctypes.byref(mid), _ptr(S), _ptr(G), msg, len(msg))
+    if rc != SIMINF_OK:
+        err = SiminfError(rc, "siminf_define_model: " + msg.value.decode(errors="replace"))
+        raise err
+    out = dict(id=int(mid.value), S=S.reshape(nc, nt, order="F"), G=G.reshape(nt, nt, order="F"))
+    _defined[key] = out
+    return out
+
+
+def generated_source(model_id: int) -> str:
+    lib = load()
+    need = ctypes.c_size_t(0)
+    lib.siminf_generated_source(model_id, None, 0, ctypes.byref(need))
+    buf = ctypes.create_string_buffer(need.value)
+    if lib.siminf_generated_source(model_id, buf, len(buf), None) != SIMINF_OK:
+        raise SiminfError(SIMINF_E_ARG, "siminf_generated_source")
+    return buf.value.decode()
+
+
 def _marshal(spec, keep: list) -> Spec:
     """Fill a siminf_spec from a model specification object (see workloads)."""
-    S = np.asarray(spec.S)
+    gen = None
+    if getattr(spec, "mparse", None) is not None:
+        mp = spec.mparse
+        gen = define_model(mp["transitions"], mp["compartments"], mp.get("gdata_names", ()),
+                           mp.get("ldata_names", ()), mp.get("v_names", ()), spec.E, spec.N)
+        S, G = gen["S"], gen["G"]
+    else:
+        S, G = np.asarray(spec.S), np.asarray(spec.G)
     Nc, Nt = S.shape
     u0 = _c(spec.u0, np.int32)
     Nn = u0.shape[0]
@@ -145,7 +214,7 @@ def _marshal(spec, keep: list) -> Spec:
     ld = _c(np.asarray(spec.ldata, dtype=np.float64).reshape(Nn, -1), np.float64)
     E = np.asarray(spec.E)
     N = np.asarray(spec.N)
-    arrays = dict(S=_c(S.ravel(order="F"), np.int32), G=_c(np.asarray(spec.G).ravel(order="F"), np.int32),
+    arrays = dict(S=_c(S.ravel(order="F"), np.int32), G=_c(np.asarray(G).ravel(order="F"), np.int32),
                   u0=u0, v0=v0, ldata=ld, gdata=_c(spec.gdata, np.float64),
                   tspan=_c(spec.tspan, np.float64), E=_c(E.ravel(order="F"), np.int32),
                   N=_c(N.ravel(order="F"), np.int32))
@@ -155,7 +224,7 @@ def _marshal(spec, keep: list) -> Spec:
     arrays["ev_prop"] = _c(ev["proportion"], np.float64)
     keep.append(arrays)
     s = Spec()
-    s.model = int(spec.model)
+    s.model = gen["id"] if gen is not None else int(spec.model)
     s.Nc, s.Nt, s.Nn = Nc, Nt, Nn
     s.Nv, s.Nld = v0.shape[1], ld.shape[1]
     s.Ngd, s.Ntspan = arrays["gdata"].size, arrays["tspan"].size

@@ -69,6 +69,10 @@ class ModelSpec:
     # SISe_sp: the sparse distance matrix of section 4.2 in compressed
     # columns, dict(ptr (Nn+1,), idx (nnz,), dist (nnz,)); None otherwise
     neighbours: dict = None
+    # a model given as transition strings (section 5.1):
+    # dict(transitions, compartments, gdata_names, ldata_names, v_names);
+    # S and G are then None (each side derives them from the strings)
+    mparse: dict = None
 
     @property
     def Nn(self) -> int:
@@ -76,6 +80,8 @@ class ModelSpec:
 
     @property
     def Nc(self) -> int:
+        if self.S is None:
+            return len(self.mparse["compartments"])
         return int(self.S.shape[0])
 
     @property
@@ -488,3 +494,164 @@ def mlp_init(dims, seed):
         lim = np.sqrt(6.0 / dims[i])
         params.append((rng.uniform(-lim, lim, (dims[i + 1], dims[i])), np.zeros(dims[i + 1])))
     return params
+
+
+# ---- models given as transition strings (section 5.1) -------------------
+
+MPARSE = -1  # model id of a spec whose model is given by transition strings
+
+
+def mparse_spec(transitions, compartments, u0, tspan, gdata=None, ldata=None, v0=None, E=None, N=None,
+                events=None, name="mparse") -> ModelSpec:
+    """A spec whose model is given as transition strings "from -> propensity
+    -> to" over the named compartments; gdata, ldata and v0 are dicts name ->
+    value (gdata) or name -> per-node values (ldata, v0), in the order the
+    names are given.  E and N (Nc x columns) are the select and shift
+    matrices of the events."""
+    u0 = np.ascontiguousarray(u0, dtype=np.int32).reshape(-1, len(compartments))
+    Nn = len(u0)
+    gdata = dict(gdata or {})
+    ldata = dict(ldata or {})
+    v0 = dict(v0 or {})
+    ld = (np.stack([np.broadcast_to(np.asarray(x, np.float64), (Nn,)) for x in ldata.values()], 1)
+          if ldata else _empty_nodes(Nn, 0))
+    vv = (np.stack([np.broadcast_to(np.asarray(x, np.float64), (Nn,)) for x in v0.values()], 1)
+          if v0 else _empty_nodes(Nn, 0))
+    nc = len(compartments)
+    E = np.zeros((nc, 0), np.int32) if E is None else np.asarray(E, dtype=np.int32).reshape(nc, -1)
+    N = np.zeros((nc, 0), np.int32) if N is None else np.asarray(N, dtype=np.int32).reshape(nc, -1)
+    spec = ModelSpec(MPARSE, None, None, u0, vv, ld, np.asarray(list(gdata.values()), dtype=np.float64),
+                     np.asarray(tspan, dtype=np.float64), E, N,
+                     events if events is not None else empty_events(), name)
+    spec.mparse = dict(transitions=list(transitions), compartments=list(compartments),
+                       gdata_names=list(gdata), ldata_names=list(ldata), v_names=list(v0))
+    return spec
+
+
+INCIDENCE_SIR = (["S -> b*S*I/(S+I+R) -> I + Icum", "I -> g*I -> R"], ["S", "I", "Icum", "R"])
+
+
+def incidence_sir(n=1000, days=150, S0=99, I0=1, b=0.16, g=0.077) -> ModelSpec:
+    """The incidence example of section 5.1: SIR with a counter Icum of the
+    infections, n identical closed nodes (99 susceptible, 1 infected)."""
+    tr, comp = INCIDENCE_SIR
+    u0 = np.tile([S0, I0, 0, 0], (n, 1))
+    return mparse_spec(tr, comp, u0, np.arange(1, days + 1), gdata=dict(b=b, g=g), name=f"mparse-sir-icum-{n}")
+
+
+def vaccination_example(seed=21, Nn=1600, days=300, vaccinate=True, b=0.16, g=0.077, infected=1) -> ModelSpec:
+    """The vaccination example of section 5.1.2 on synthetic herds: S, I,
+    Icum, R, V; births into S (E column 1), deaths and movements over S, I,
+    R, V (column 2), vaccination as internal transfers of 80% of S, I and R
+    (column 3) shifted to V by the N column (S +4, I +3, R +1), 50 herds a
+    day from day 21 until every herd is done; one infected animal in each of
+    `infected` random herds (one in the example).  Herd sizes and the birth, death and movement events follow the
+    SIR-with-events generator (the example's data sets are not available)."""
+    rng = np.random.default_rng(seed)
+    size = np.clip(np.round(rng.lognormal(np.log(100.0), 1.0, Nn)), 1, 5000).astype(np.int64)
+    u0 = np.zeros((Nn, 5), np.int64)
+    u0[:, 0] = size
+    for j in rng.choice(Nn, size=infected, replace=False):
+        take = min(int(u0[j, 0]), 1)
+        u0[j, 0] -= take
+        u0[j, 1] += take
+    E = np.array([[1, 1, 1], [0, 1, 1], [0, 0, 0], [0, 1, 1], [0, 1, 0]], np.int32)
+    N = np.array([[4], [3], [0], [1], [0]], np.int32)
+    ev = _keep_nonempty(_demographic_events(rng, Nn, size, days, birth=0.0005, exit_=0.0003, ship_frac=0.005,
+                                            select_all=1, birth_select=0), size)
+    if vaccinate:
+        rows = [(INTTRANS, 21 + k // 50, k, 0, 0, 0.8, 2, 0) for k in range(Nn) if 21 + k // 50 <= days]
+        ev = concat_events(ev, make_events(rows))
+    tr = ["S -> b*S*I/(S+I+R+V) -> I + Icum", "I -> g*I -> R"]
+    return mparse_spec(tr, ["S", "I", "Icum", "R", "V"], u0, np.arange(1, days + 1), gdata=dict(b=b, g=g),
+                       E=E, N=N, events=ev, name=f"mparse-vaccination-{Nn}x{days}")
+
+
+def _keep_nonempty(ev: dict, size) -> dict:
+    """The events without the exits and external transfers that would leave
+    a node with no animals (the propensity b*S*I/(S+I+R+V) of the
+    vaccination example is 0/0 in an empty herd).  Totals are followed in
+    the order a day applies the events: every node's exits, then its
+    births, then the external transfers in input order."""
+    tot = np.asarray(size, dtype=np.int64).copy()
+    keep = np.ones(len(ev["time"]), dtype=bool)
+    order = np.lexsort((np.arange(len(ev["time"])), ev["event"] == EXTTRANS, ev["event"], ev["time"]))
+    for e in order:
+        ty, node, n = int(ev["event"][e]), int(ev["node"][e]), int(ev["n"][e])
+        moved = n if n > 0 else int(np.floor(float(ev["proportion"][e]) * tot[node] + 0.5))
+        if ty == ENTER:
+            tot[node] += n
+        elif ty in (EXIT, EXTTRANS):
+            if moved >= tot[node]:
+                keep[e] = False
+                continue
+            tot[node] -= moved
+            if ty == EXTTRANS:
+                tot[int(ev["dest"][e])] += moved
+    return {k: np.asarray(v)[keep].copy() for k, v in ev.items()}
+
+
+def age_structured_sis(seed=31, Nn=400, days=200, gamma=0.1, beta=0.3) -> ModelSpec:
+    """An age-structured SIS in three age categories, with the compartments
+    and scheduled events of the illustration in Appendix B: S1 I1 S2 I2 S3
+    I3; infection within a category at beta*S_a*I/N, recovery at gamma*I_a;
+    events: births into S1 (E column 1), exits from each category (columns
+    4-6: {S_a, I_a}), ageing of categories 1 and 2 as internal transfers
+    shifted by the N columns (S1->S2, I1->I2; S2->S3, I2->I3), and movements
+    of single animals of a category between nodes.  The generator follows
+    each category's total in the order a day applies the events (exits,
+    births, ageing, movements out, then movements in), so no event
+    overdraws."""
+    rng = np.random.default_rng(seed)
+    comp = ["S1", "I1", "S2", "I2", "S3", "I3"]
+    Ntot = "(S1+I1+S2+I2+S3+I3)"
+    Itot = "(I1+I2+I3)"
+    tr = []
+    for a in (1, 2, 3):
+        tr.append(f"S{a} -> beta*S{a}*{Itot}/{Ntot} -> I{a}")
+        tr.append(f"I{a} -> gamma*I{a} -> S{a}")
+    size = np.maximum(np.round(rng.lognormal(np.log(60.0), 0.6, (Nn, 3))), 1).astype(np.int64)
+    u0 = np.zeros((Nn, 6), np.int64)
+    u0[:, 0], u0[:, 2], u0[:, 4] = size[:, 0], size[:, 1], size[:, 2]
+    inf = rng.choice(Nn, size=max(1, Nn // 10), replace=False)
+    take = np.minimum(u0[inf, 0], 2)
+    u0[inf, 0] -= take
+    u0[inf, 1] += take
+    # E columns: 1-3 {S_a} (births into the first), 4-6 {S_a, I_a}
+    E = np.zeros((6, 6), np.int32)
+    for a in range(3):
+        E[2 * a, a] = 1
+        E[2 * a, 3 + a] = E[2 * a + 1, 3 + a] = 1
+    N = np.zeros((6, 2), np.int32)
+    N[0, 0] = N[1, 0] = 2  # S1 -> S2, I1 -> I2
+    N[2, 1] = N[3, 1] = 2  # S2 -> S3, I2 -> I3
+    tot = u0.reshape(Nn, 3, 2).sum(2)  # animals per node and category
+    rows = []
+    for day in range(1, days + 1):
+        arriving = np.zeros_like(tot)
+        for i in range(Nn):
+            for a in range(3):
+                if tot[i, a] > 0 and rng.random() < 0.005:
+                    k = int(rng.integers(1, min(3, tot[i, a]) + 1))
+                    rows.append((EXIT, day, i, 0, k, 0.0, 3 + a, -1))
+                    tot[i, a] -= k
+            if rng.random() < 0.02:
+                k = int(rng.integers(1, 4))
+                rows.append((ENTER, day, i, 0, k, 0.0, 0, -1))
+                tot[i, 0] += k
+            for a, every, prop in ((0, 30, 0.25), (1, 60, 0.2)):
+                if day % every == 0 and tot[i, a] > 0:
+                    rows.append((INTTRANS, day, i, 0, 0, prop, 3 + a, a))
+                    moved = int(np.floor(prop * tot[i, a] + 0.5))
+                    tot[i, a] -= moved
+                    tot[i, a + 1] += moved
+            if rng.random() < 0.01:
+                a = int(rng.integers(0, 3))
+                dst = int(rng.integers(0, Nn))
+                if tot[i, a] > 1 and dst != i:
+                    rows.append((EXTTRANS, day, i, dst, 1, 0.0, 3 + a, -1))
+                    tot[i, a] -= 1
+                    arriving[dst, a] += 1
+        tot += arriving
+    return mparse_spec(tr, comp, u0, np.arange(0, days + 1), gdata=dict(beta=beta, gamma=gamma),
+                       E=E, N=N, events=make_events(rows), name=f"mparse-age-sis-{Nn}x{days}")
