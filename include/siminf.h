@@ -325,6 +325,21 @@ int siminf_wait(siminf_model *m);
  * undefined. */
 int siminf_trajectory(siminf_model *m, int32_t run, int32_t *U, double *V, int32_t dst_is_device);
 
+/* Selected entries of run `run`'s trajectory (Table 1, U_sparse and
+ * V_sparse): the nonzero pattern of a sparse (Nn*width) x Ntspan matrix in
+ * compressed columns -- col_ptr[0..Ntspan] (col_ptr[0] = 0, nondecreasing,
+ * col_ptr[Ntspan] = nnz) and row_idx[0..nnz), row = node*width + c in the
+ * run's own node numbering -- and the values written, as binary64, to
+ * values[0..nnz) in pattern order: U (which = 0, width Nc) or V (which = 1,
+ * width Nv) at tspan index m for the entries of column m.  The pattern is
+ * host memory; values is host memory, or device memory when dst_is_device.
+ * The model records in SIMINF_RECORD_FULL (the full trajectory stays on the
+ * device; only the selected entries are copied out).  Returns SIMINF_E_ARG
+ * for a bad pattern (checked before any device work), else as
+ * siminf_trajectory. */
+int siminf_trajectory_sparse(siminf_model *m, int32_t run, int32_t which, int64_t nnz, const int64_t *col_ptr,
+                             const int32_t *row_idx, double *values, int32_t dst_is_device);
+
 /* Copies the per-run compartment sums over all nodes at each tspan point
  * (the numerators and denominators of prevalence() in section 4.2), int64
  * [runs][Ntspan][Nc] row-major, to sums (host, or device if dst_is_device).

@@ -201,6 +201,9 @@ int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, si
                       bool lane_queue = false);
 hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nmajor,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
+hipError_t launch_sparse_gather(const int32_t* U, const double* V, int width, int n, int ntspan, int nmajor,
+                                const int32_t* pos, const int64_t* col_ptr, const int32_t* row_idx, long long nnz,
+                                double* out, hipStream_t st);
 // generated models (generated.cpp): launch through the run-time compiled module
 hipError_t generated_launch(int id, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st);
 int generated_blocks_per_cu(int id, int mode, int pipeline, int block, size_t shmem);

@@ -1251,6 +1251,46 @@ int siminf_trajectory(siminf_model* m, int32_t run, int32_t* U, double* V, int32
     return status;
 }
 
+int siminf_trajectory_sparse(siminf_model* m, int32_t run, int32_t which, int64_t nnz, const int64_t* col_ptr,
+                             const int32_t* row_idx, double* values, int32_t dst_is_device) {
+    if (!m || run < 0 || run >= m->R || (which != 0 && which != 1) || nnz < 0 || !col_ptr ||
+        (nnz > 0 && (!row_idx || !values)))
+        return SIMINF_E_ARG;
+    if (m->record != SIMINF_RECORD_FULL || !m->ran) return SIMINF_E_ARG;
+    const RunInfo& ri = m->runs[run];
+    const Group& g = m->groups[ri.group];
+    const int width = which == 0 ? g.shape.nc : g.shape.nv;
+    const int64_t rows = (int64_t)ri.nn * width;
+    // the pattern: nondecreasing column pointers from 0 to nnz, rows in range
+    if (col_ptr[0] != 0 || col_ptr[m->ntspan] != nnz) return SIMINF_E_ARG;
+    for (int k = 0; k < m->ntspan; ++k)
+        if (col_ptr[k + 1] < col_ptr[k]) return SIMINF_E_ARG;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (row_idx[e] < 0 || row_idx[e] >= rows) return SIMINF_E_ARG;
+    const int status = finish(m);
+    if (status == SIMINF_E_DEVICE) return status;
+    if (nnz == 0) return status;
+    // pattern and values through one device allocation of this call
+    const size_t b_ptr = sizeof(int64_t) * ((size_t)m->ntspan + 1), b_idx = sizeof(int32_t) * (size_t)nnz;
+    const size_t b_out = dst_is_device ? 0 : sizeof(double) * (size_t)nnz;
+    const size_t off_idx = (b_ptr + 255) & ~(size_t)255, off_out = (off_idx + b_idx + 255) & ~(size_t)255;
+    char* buf = nullptr;
+    if (hipMalloc((void**)&buf, off_out + b_out) != hipSuccess) return SIMINF_E_ALLOC;
+    double* out = dst_is_device ? values : (double*)(buf + off_out);
+    hipStream_t st = m->last_stream;
+    int rc = status;
+    if (hipMemcpy(buf, col_ptr, b_ptr, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(buf + off_idx, row_idx, b_idx, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_sparse_gather(which == 0 ? g.p.U : nullptr, which == 0 ? nullptr : g.p.V, width, g.n, m->ntspan,
+                             g.p.nmajor, m->d_pos + ri.noff, (const int64_t*)buf, (const int32_t*)(buf + off_idx),
+                             nnz, out, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess ||
+        (!dst_is_device && hipMemcpy(values, out, b_out, hipMemcpyDeviceToHost) != hipSuccess))
+        rc = SIMINF_E_DEVICE;
+    (void)hipFree(buf);
+    return rc;
+}
+
 int siminf_sums(siminf_model* m, int64_t* sums, int32_t dst_is_device) {
     if (!m || !sums || m->record != SIMINF_RECORD_SUMS || !m->ran) return SIMINF_E_ARG;
     const int status = finish(m);

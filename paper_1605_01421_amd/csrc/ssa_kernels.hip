@@ -1780,6 +1780,30 @@ __global__ void gather_kernel(const int32_t* U, const double* V, int nc, int nv,
     }
 }
 
+// Sparse copy-out (Table 1, U_sparse / V_sparse): entry e of a compressed-
+// column pattern over the (Nn*width) x Ntspan matrix (column m = tspan
+// index, row = node*width + c) takes the recorded value, as binary64.
+__global__ void sparse_gather_kernel(const int32_t* U, const double* V, int width, int n, int ntspan, int nmajor,
+                                     const int32_t* pos, const int64_t* col_ptr, const int32_t* row_idx,
+                                     long long nnz, double* out) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz;
+         e += (long long)gridDim.x * blockDim.x) {
+        // the column of entry e: the last m with col_ptr[m] <= e
+        int lo = 0, hi = ntspan;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (col_ptr[mid] <= e)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int row = row_idx[e];
+        const int k = pos[row / width], c = row % width;
+        const size_t at = rec_index(lo, c, k, width, ntspan, n, nmajor);
+        out[e] = U ? (double)U[at] : V[at];
+    }
+}
+
 // One workgroup per (set, tspan index): prevalence of every replicate, rank
 // sort (ties by replicate index), type-7 quantiles.
 __global__ void prevalence_kernel(const unsigned long long* sums, int ntspan, int nc, int case_c, uint32_t mask,
@@ -1888,6 +1912,15 @@ hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int 
     long long total = (long long)ntspan * nn;
     int blocks = (int)std::max<long long>(1, std::min<long long>((total + 255) / 256, 8192));
     gather_kernel<<<blocks, 256, 0, st>>>(U, V, nc, nv, n, ntspan, nmajor, pos, nn, Uo, Vo);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_gather(const int32_t* U, const double* V, int width, int n, int ntspan, int nmajor,
+                                const int32_t* pos, const int64_t* col_ptr, const int32_t* row_idx, long long nnz,
+                                double* out, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    const int blocks = (int)std::max<long long>(1, std::min<long long>((nnz + 255) / 256, 8192));
+    sparse_gather_kernel<<<blocks, 256, 0, st>>>(U, V, width, n, ntspan, nmajor, pos, col_ptr, row_idx, nnz, out);
     return hipGetLastError();
 }
 

@@ -74,6 +74,8 @@ SIGNATURES = {
     "siminf_wait": (ctypes.c_int, [_P]),
     "siminf_trajectory": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "siminf_sums": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "siminf_trajectory_sparse": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P,
+                                                ctypes.c_int32]),
     "siminf_counters": (ctypes.c_int, [_P, _P]),
     "siminf_shape": (ctypes.c_int, [_P, _P]),
     "siminf_error_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -401,6 +403,23 @@ class Model:
         if rc != SIMINF_OK:
             raise SiminfError(rc, "siminf_trajectory")
         return U, V
+
+    def trajectory_sparse(self, pattern, which: str = "U", run: int = 0) -> np.ndarray:
+        """The entries of U (or V) at the nonzeros of `pattern`, a
+        scipy.sparse matrix of shape (Nn*Nc (or Nn*Nv), Ntspan) in the
+        paper's layout (Table 1, U_sparse / V_sparse); returns a CSC matrix
+        with the same pattern and the recorded values (binary64)."""
+        import scipy.sparse as sp
+        P = sp.csc_matrix(pattern)
+        P.sort_indices()
+        col_ptr = _c(P.indptr, np.int64)
+        rows = _c(P.indices, np.int32)
+        vals = np.zeros(rows.size, dtype=np.float64)
+        rc = self._lib.siminf_trajectory_sparse(self._h, run, 0 if which == "U" else 1, rows.size, _ptr(col_ptr),
+                                                _ptr(rows), _ptr(vals), 0)
+        if rc != SIMINF_OK:
+            raise SiminfError(rc, "siminf_trajectory_sparse")
+        return sp.csc_matrix((vals, P.indices.copy(), P.indptr.copy()), shape=P.shape)
 
     def sums(self) -> np.ndarray:
         """Per-run compartment sums over nodes, int64 (runs, Ntspan, Nc_max)."""

@@ -645,3 +645,33 @@ def test_wide_node_event_windows(lib, opts, transfers):
     _compare(m, ref, what=f"event windows {opts}")
     c = m.counters()
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
+def test_sparse_trajectory(lib):
+    """Table 1's U_sparse / V_sparse: the entries of U and V at a random
+    sparse pattern (in the paper's layout: row node*width + c, column tspan
+    index), empty columns included, equal the oracle's trajectory there; a
+    pattern out of range is refused."""
+    import scipy.sparse as sp
+    spec = W.sise_with_events(seed=4, Nn=300, days=60)
+    m, ref, rc = _run_both(lib, spec, 9, 2)
+    assert rc == 0
+    rng = np.random.default_rng(3)
+    T = ref["U"].shape[0]
+    for which, arr in (("U", ref["U"]), ("V", ref["V"])):
+        Nn, width = arr.shape[1], arr.shape[2]
+        dense = np.zeros((Nn * width, T))
+        mask = rng.random(dense.shape) < 0.02
+        mask[:, 5] = False  # an empty column
+        dense[mask] = 1.0
+        P = sp.csc_matrix(dense)
+        P.sort_indices()
+        got = m.trajectory_sparse(P, which)
+        assert np.array_equal(got.indptr, P.indptr) and np.array_equal(got.indices, P.indices)
+        want = arr.transpose(1, 2, 0).reshape(Nn * width, T)  # [node*width + c, t], the paper's layout
+        cols = np.repeat(np.arange(T), np.diff(P.indptr))
+        assert got.data.size == mask.sum()
+        assert np.array_equal(got.data, want[P.indices, cols].astype(np.float64)), which
+    bad = sp.csc_matrix(([1.0], ([spec.Nn * 2], [0])), shape=(spec.Nn * 2 + 1, T))
+    with pytest.raises(lib.SiminfError):
+        m.trajectory_sparse(bad, "U")
