@@ -61,7 +61,9 @@ class _Model(ctypes.Structure):
         ("E", ctypes.c_void_p), ("N", ctypes.c_void_p),
         ("Nnb", ctypes.c_int32), ("nb_ptr", ctypes.c_void_p), ("nb_idx", ctypes.c_void_p),
         ("nb_dist", ctypes.c_void_p), ("prog_off", ctypes.c_void_p), ("prog", ctypes.c_void_p),
-        ("consts", ctypes.c_void_p)]
+        ("consts", ctypes.c_void_p), ("solver", ctypes.c_int32)]
+
+SOLVERS = {"ssm": 0, "aem": 1}
 
 # the model id the C oracle reads as "generated from transition strings"
 MODEL_GENERATED = 64
@@ -101,7 +103,7 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
 
 
-def run(spec, seed: int, stream: int = 0, nthreads: int | None = None) -> dict:
+def run(spec, seed: int, stream: int = 0, nthreads: int | None = None, solver: str = "ssm") -> dict:
     """Run one trajectory of ``spec`` with Philox key ``seed`` and ``stream``.
 
     Returns a dict with ``U`` (Ntspan, Nn, Nc) int32, ``V`` (Ntspan, Nn, Nv)
@@ -139,6 +141,7 @@ def run(spec, seed: int, stream: int = 0, nthreads: int | None = None) -> dict:
     keep["ev_prop"] = _c(ev["proportion"], np.float64)
     m = _Model()
     m.model = MODEL_GENERATED if gen is not None else int(spec.model)
+    m.solver = SOLVERS[solver]
     if gen is not None:
         for f in ("prog_off", "prog"):
             keep[f] = _c(gen[f], np.int32)

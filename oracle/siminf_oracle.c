@@ -113,6 +113,7 @@ typedef struct {
      * prog[prog_off[j] .. prog_off[j+1]) over the constants consts[] */
     const int32_t *prog_off, *prog;
     const double *consts;
+    int32_t solver; /* SOLVER_SSM or SOLVER_AEM */
 } oracle_model;
 
 /* postfix program operations of a generated model's propensity: the low 8
@@ -220,6 +221,12 @@ double oracle_plog(double x) {
  *     counter = (b, 0, e, (stream & 0xFFFFFF) | 1<<24)            */
 #define PURPOSE_SSA 0u
 #define PURPOSE_EVENT 1u
+#define PURPOSE_AEM 2u /* the all events method's per-channel streams */
+
+/* solvers (section 3.4): the split-step direct method, and the all events
+ * method, whose transition channels each draw from a private stream */
+#define SOLVER_SSM 0
+#define SOLVER_AEM 1
 
 typedef struct {
     uint32_t key[2];
@@ -465,6 +472,17 @@ static int pts_fn(int model, double *v_new, const int32_t *u, const double *v,
     return 0;
 }
 
+/* The k-th unit exponential of channel j of node i (all events method):
+ * -log of the uniform from the first two words of the Philox block
+ * (k, j, i, stream | PURPOSE_AEM << 24). */
+static double aem_exp(uint64_t seed, uint32_t stream, int i, int j, uint32_t k) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {k, (uint32_t)j, (uint32_t)i, (stream & 0xFFFFFFu) | (PURPOSE_AEM << 24)};
+    uint32_t r[4];
+    oracle_philox(key, ctr, r);
+    return -oracle_plog(oracle_uniform(r[0], r[1]));
+}
+
 /* ---- error keys ------------------------------------------------------
  * (boundary index, phase, index) ordered lexicographically, packed into a
  * 64-bit key so that the smallest key is the first error in the serial
@@ -587,6 +605,8 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
     err[0] = 0;
     err[1] = err[2] = err[3] = -1;
     counters[0] = counters[1] = counters[2] = 0;
+    if (m->solver != SOLVER_SSM && m->solver != SOLVER_AEM)
+        return err[0] = OR_E_ARG;
     if (m->model >= MODEL_GENERATED_FIRST) {
         /* a generated model has the sizes it was given */
         if (!m->prog_off || !m->prog || m->Nc < 1 || m->Nt < 1 || m->Nt > 32 || m->Nv > 64)
@@ -628,13 +648,26 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
     uint64_t *node_err = malloc(sizeof(uint64_t) * (size_t)(Nn ? Nn : 1));
     uint64_t *node_trans = calloc((size_t)(Nn ? Nn : 1), sizeof(uint64_t));
     uint64_t *node_events = calloc((size_t)(Nn ? Nn : 1), sizeof(uint64_t));
+    /* all events method: per node and channel the integrated rate, the
+     * next firing level and the index of the next exponential */
+    const size_t nch = (size_t)(Nn ? Nn : 1) * (size_t)Nt;
+    double *aem_T = m->solver == SOLVER_AEM ? calloc(nch, sizeof(double)) : NULL;
+    double *aem_P = m->solver == SOLVER_AEM ? malloc(nch * sizeof(double)) : NULL;
+    uint32_t *aem_K = m->solver == SOLVER_AEM ? malloc(nch * sizeof(uint32_t)) : NULL;
     if (!u || !v || !v_next || !order || !e1_start || !e1_list || !e1_cursor ||
-        !e2_list || !node_err || !node_trans || !node_events) {
+        !e2_list || !node_err || !node_trans || !node_events ||
+        (m->solver == SOLVER_AEM && (!aem_T || !aem_P || !aem_K))) {
         free(u); free(v); free(v_next); free(order); free(e1_start); free(e1_list);
         free(e1_cursor); free(e2_list); free(node_err); free(node_trans);
-        free(node_events);
+        free(node_events); free(aem_T); free(aem_P); free(aem_K);
         return err[0] = OR_E_ALLOC;
     }
+    if (m->solver == SOLVER_AEM)
+        for (int i = 0; i < Nn; ++i)
+            for (int j = 0; j < Nt; ++j) {
+                aem_P[(size_t)i * Nt + j] = aem_exp(seed, stream, i, j, 0);
+                aem_K[(size_t)i * Nt + j] = 1;
+            }
     memcpy(u, m->u0, sizeof(int32_t) * (size_t)Nc * Nn);
     if (Nv)
         memcpy(v, m->v0, sizeof(double) * (size_t)Nv * Nn);
@@ -720,6 +753,70 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
                 continue;
             }
             double ti = t;
+            if (m->solver == SOLVER_AEM) {
+                /* All events method (section 3.4): channel j fires when its
+                 * integrated rate Tj reaches Pj, the running sum of the unit
+                 * exponentials of its private stream.  The next channel is
+                 * the one with the least (Pj - Tj)/wj (the lowest j on a
+                 * tie); the others' integrals advance by wk tau, the fired
+                 * one's becomes Pj and Pj takes its next exponential.  At
+                 * the day boundary every integral advances to T; the
+                 * integrals and sums carry over to the next day. */
+                double *Ti = aem_T + (size_t)i * Nt, *Pi = aem_P + (size_t)i * Nt;
+                uint32_t *Ki = aem_K + (size_t)i * Nt;
+                uint32_t k = 0;
+                for (;;) {
+                    int n = -1;
+                    double best = 0.0;
+                    for (int j = 0; j < Nt; ++j) {
+                        if (w[j] > 0.0) {
+                            double tau = (Pi[j] - Ti[j]) / w[j];
+                            if (n < 0 || tau < best) {
+                                best = tau;
+                                n = j;
+                            }
+                        }
+                    }
+                    if (n < 0)
+                        break; /* no positive rate: the integrals stay */
+                    if (k == OR_STEP_LIMIT) {
+                        bad = OR_E_STEP_LIMIT;
+                        break;
+                    }
+                    k++;
+                    double tn = ti + best;
+                    if (tn >= T) {
+                        double rest = T - ti;
+                        for (int j = 0; j < Nt; ++j)
+                            Ti[j] = Ti[j] + w[j] * rest;
+                        break;
+                    }
+                    for (int j = 0; j < Nt; ++j)
+                        if (j != n)
+                            Ti[j] = Ti[j] + w[j] * best;
+                    Ti[n] = Pi[n];
+                    Pi[n] = Pi[n] + aem_exp(seed, stream, i, n, Ki[n]);
+                    Ki[n] += 1;
+                    ti = tn;
+                    for (int c = 0; c < Nc; ++c) {
+                        ui[c] += m->S[(size_t)n * Nc + c];
+                        if (ui[c] < 0)
+                            bad = OR_E_NEG_STATE;
+                    }
+                    node_trans[i] += 1;
+                    if (bad)
+                        break;
+                    for (int j = 0; j < Nt; ++j) {
+                        if (m->G[(size_t)n * Nt + j] != 0) {
+                            w[j] = rate_any(m, j, ui, vi, ld, m->gdata);
+                            if (!(w[j] >= 0.0) || !isfinite(w[j]))
+                                bad = OR_E_BAD_RATE;
+                        }
+                    }
+                    if (bad)
+                        break;
+                }
+            } else {
             uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
             uint32_t ctr[4] = {0, Tword, (uint32_t)i,
                                (stream & 0xFFFFFFu) | (PURPOSE_SSA << 24)};
@@ -777,6 +874,7 @@ int oracle_run(const oracle_model *m, uint64_t seed, uint32_t stream,
                 }
                 if (bad)
                     break;
+            }
             }
             if (bad) {
                 node_err[i] = make_key(b, PH_SSA, i, bad);
@@ -882,6 +980,9 @@ done:
     free(u); free(v); free(v_next); free(order); free(e1_start); free(e1_list);
     free(e1_cursor); free(e2_list); free(node_err); free(node_trans);
     free(node_events);
+    free(aem_T);
+    free(aem_P);
+    free(aem_K);
     return (int)err[0];
 }
 
