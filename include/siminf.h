@@ -263,6 +263,20 @@ typedef struct {
     int32_t batch;     /* lane queue: lanes of a wavefront that wait at the end
                           of a day (or without a node) before the wavefront
                           serves them together, 1..64; 0 = 16 */
+    int32_t solver;    /* section 3.4: 0 the split-step direct method (default);
+                          1 the all events method: every transition channel
+                          of a node fires when its integrated rate reaches
+                          the running sum of unit exponentials drawn from the
+                          channel's own stream (Philox block (k, j, node,
+                          stream | 2<<24), -log of the uniform from its first
+                          two words, k = 0, 1, ... per channel); the channel
+                          with the least (P_j - T_j)/w_j fires, the lowest j
+                          on a tie, unless that time crosses the day
+                          boundary, where every integral advances to it and
+                          carries over.  Same law, other draws; one lane per
+                          node (no lane queue, wavefront-wide nodes or
+                          groups); checks and error keys as the direct
+                          method's.  Anything else: SIMINF_E_ARG. */
 } siminf_options;
 
 typedef struct siminf_model siminf_model;

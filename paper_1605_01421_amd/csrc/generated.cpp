@@ -262,7 +262,7 @@ bool parse_side(const std::string& side, const std::map<std::string, int>& comp,
 
 struct DeviceModule {
     hipModule_t mod = nullptr;
-    hipFunction_t fn[3][2] = {};  // [mode: free, barrier, dataflow][pipelined]
+    hipFunction_t fn[3][3] = {};  // [mode: free, barrier, dataflow][direct, pipelined direct, all events]
 };
 
 struct Generated {
@@ -272,7 +272,7 @@ struct Generated {
     int ecols = 0, ncols = 0;
     std::string source;
     std::vector<char> code;
-    std::string lowered[3][2];
+    std::string lowered[3][3];
     std::map<int, DeviceModule> per_device;
 };
 
@@ -280,10 +280,13 @@ std::mutex g_mu;         // the registry
 std::mutex g_define_mu;  // one definition at a time (ids are handed out in order)
 std::vector<std::unique_ptr<Generated>> g_models;
 
-const char* const KERNEL_EXPR[3][2] = {
-    {"siminf::free_kernel<siminf::ModelGen, false, false>", "siminf::free_kernel<siminf::ModelGen, true, false>"},
-    {"siminf::sync_kernel<siminf::ModelGen, false>", "siminf::sync_kernel<siminf::ModelGen, true>"},
-    {"siminf::flow_kernel<siminf::ModelGen, false, false>", "siminf::flow_kernel<siminf::ModelGen, true, false>"},
+const char* const KERNEL_EXPR[3][3] = {
+    {"siminf::free_kernel<siminf::ModelGen, false, false, false>", "siminf::free_kernel<siminf::ModelGen, true, false, false>",
+     "siminf::free_kernel<siminf::ModelGen, false, false, true>"},
+    {"siminf::sync_kernel<siminf::ModelGen, false, false>", "siminf::sync_kernel<siminf::ModelGen, true, false>",
+     "siminf::sync_kernel<siminf::ModelGen, false, true>"},
+    {"siminf::flow_kernel<siminf::ModelGen, false, false, false>", "siminf::flow_kernel<siminf::ModelGen, true, false, false>",
+     "siminf::flow_kernel<siminf::ModelGen, false, false, true>"},
 };
 
 void put_message(char* msg, size_t cap, const std::string& text) {
@@ -308,7 +311,7 @@ DeviceModule* module_on_device(Generated* g) {
     DeviceModule dm;
     if (hipModuleLoadData(&dm.mod, g->code.data()) != hipSuccess) return nullptr;
     for (int m = 0; m < 3; ++m)
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 3; ++q)
             if (hipModuleGetFunction(&dm.fn[m][q], dm.mod, g->lowered[m][q].c_str()) != hipSuccess) {
                 (void)hipModuleUnload(dm.mod);
                 return nullptr;
@@ -355,7 +358,7 @@ hipError_t generated_launch(int id, const KParams& p, int block, int blocks, siz
         dm = module_on_device(g);
     }
     if (!dm) return hipErrorInvalidImage;
-    hipFunction_t fn = dm->fn[mode_slot(p.mode)][p.pipeline ? 1 : 0];
+    hipFunction_t fn = dm->fn[mode_slot(p.mode)][p.solver == 1 ? 2 : p.pipeline ? 1 : 0];
     KParams arg = p;
     void* args[] = {&arg};
     if (p.mode == MODE_FREE)
@@ -365,15 +368,15 @@ hipError_t generated_launch(int id, const KParams& p, int block, int blocks, siz
                                             args);
 }
 
-int generated_blocks_per_cu(int id, int mode, int pipeline, int block, size_t shmem) {
+int generated_blocks_per_cu(int id, int mode, int pipeline, int block, size_t shmem, bool aem) {
     std::lock_guard<std::mutex> lk(g_mu);
     Generated* g = find(id);
     if (!g) return 0;
     DeviceModule* dm = module_on_device(g);
     if (!dm) return 0;
     int n = 0;
-    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, dm->fn[mode_slot(mode)][pipeline ? 1 : 0], block,
-                                                           shmem) != hipSuccess)
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, dm->fn[mode_slot(mode)][aem ? 2 : pipeline ? 1 : 0],
+                                                           block, shmem) != hipSuccess)
         return 0;
     return n;
 }
@@ -528,7 +531,7 @@ extern "C" int siminf_define_model(const siminf_model_def* def, int32_t* model_i
         return SIMINF_E_DEVICE;
     }
     for (int m = 0; m < 3; ++m)
-        for (int q = 0; q < 2; ++q) hiprtcAddNameExpression(prog, KERNEL_EXPR[m][q]);
+        for (int q = 0; q < 3; ++q) hiprtcAddNameExpression(prog, KERNEL_EXPR[m][q]);
     const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
     const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
@@ -542,7 +545,7 @@ extern "C" int siminf_define_model(const siminf_model_def* def, int32_t* model_i
         return SIMINF_E_DEVICE;
     }
     for (int m = 0; m < 3; ++m)
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < 3; ++q) {
             const char* lowered = nullptr;
             if (hiprtcGetLoweredName(prog, KERNEL_EXPR[m][q], &lowered) != HIPRTC_SUCCESS || !lowered) {
                 hiprtcDestroyProgram(&prog);

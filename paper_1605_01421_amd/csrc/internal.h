@@ -177,6 +177,11 @@ struct KParams {
     const int4* lchunks;         // [nlchunks] x = first node, y = end, z = run
     int32_t lq_batch;            // lanes that wait at their day's end before the
                                  // wavefront closes their days together
+    int32_t solver;              // 0 the direct method, 1 the all events method:
+    int32_t nt;                  //   transitions, and per node and channel
+    double* aem_T;               //   [nt][n] the integrated rate,
+    double* aem_P;               //   [nt][n] the level of the next firing,
+    uint32_t* aem_K;             //   [nt][n] the index of the next exponential
     int32_t coupled;             // spatial coupling of the post-time step (SISe_sp):
     const int32_t* cpl_off;      //   [n+1] each node's neighbours (internal order), then
                                  //         the nodes that list it but that it does not list
@@ -198,7 +203,7 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem,
                         hipStream_t st);
 int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem,
-                      bool lane_queue = false);
+                      bool lane_queue = false, bool aem = false);
 hipError_t launch_gather(int nc, int nv, const int32_t* U, const double* V, int n, int ntspan, int nmajor,
                          const int32_t* pos, int nn, int32_t* Uo, double* Vo, hipStream_t st);
 hipError_t launch_sparse_gather(const int32_t* U, const double* V, int width, int n, int ntspan, int nmajor,
@@ -206,7 +211,7 @@ hipError_t launch_sparse_gather(const int32_t* U, const double* V, int width, in
                                 double* out, hipStream_t st);
 // generated models (generated.cpp): launch through the run-time compiled module
 hipError_t generated_launch(int id, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st);
-int generated_blocks_per_cu(int id, int mode, int pipeline, int block, size_t shmem);
+int generated_blocks_per_cu(int id, int mode, int pipeline, int block, size_t shmem, bool aem);
 hipError_t launch_prevalence(const unsigned long long* sums, int runs, int ntspan, int nc,
                              int case_c, uint32_t mask, int reps, int k0, int nk,
                              const double* probs, int nq, float* out, hipStream_t st);

@@ -281,7 +281,7 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     KParams& p = g.p;
     p.lane_queue = 0;
     g.lq_chunk = 0;
-    if (lq_chunk > 0 && g.n_e2 == 0 && !p.coupled && !is_generated(g.model)) {
+    if (lq_chunk > 0 && g.n_e2 == 0 && !p.coupled && !is_generated(g.model) && p.solver == 0) {
         const int cus = device_cus(m);
         if (cus <= 0) return SIMINF_E_DEVICE;
         if (block == 0) block = 256;
@@ -345,8 +345,9 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         return SIMINF_OK;
     }
     if (lq_chunk > 0) return SIMINF_E_UNSUPPORTED;
-    // a generated model runs one lane per node
-    if (is_generated(g.model)) {
+    // a generated model, and the all events method, run one lane per node
+    const bool aem = p.solver == 1;
+    if (is_generated(g.model) || aem) {
         nbig = 0;
         ngrp = 0;
     }
@@ -373,14 +374,14 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
         if (want_mode == 0 || want_mode == 2) {
             int nb = nbig;
             int ng = std::min(ngrp, n - nb);
-            int per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, ng > 0, block, 0);
+            int per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, ng > 0, block, 0, false, aem);
             auto need = [&](int k, int gn) {
                 return (k + (gn + per_grp - 1) / per_grp + (n - k - gn + pack - 1) / pack + wpb - 1) / wpb;
             };
             // every wavefront must be resident: drop the groups first, then halve the wide nodes
             if (ng > 0 && (per_cu <= 0 || need(nb, ng) > per_cu * cus)) {
                 ng = 0;
-                per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, false, block, 0);
+                per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, false, block, 0, false, aem);
             }
             while (nb > 0 && per_cu > 0 && need(nb, ng) > per_cu * cus) nb /= 2;
             if (per_cu > 0 && need(nb, std::min(ng, n - nb)) <= per_cu * cus) {
@@ -398,13 +399,13 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
             nbig = 0;
             ngrp = 0;
             pack = WAVE;  // the barrier kernel strides over nodes 64 to a wavefront
-            const int per_cu = max_blocks_per_cu(g.model, MODE_BARRIER, p.pipeline, false, block, 0);
+            const int per_cu = max_blocks_per_cu(g.model, MODE_BARRIER, p.pipeline, false, block, 0, false, aem);
             if (per_cu <= 0) return SIMINF_E_DEVICE;
             blocks = std::max(1, std::min(per_cu * cus, (n + block - 1) / block));
             if (m->opt.max_blocks > 0) blocks = std::min(blocks, m->opt.max_blocks);
         }
     } else {
-        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, p.pipeline, ngrp > 0, block, 0);
+        const int per_cu = max_blocks_per_cu(g.model, MODE_FREE, p.pipeline, ngrp > 0, block, 0, false, aem);
         if (per_cu <= 0) return SIMINF_E_DEVICE;
         const int chunks = nbig + (ngrp + per_grp - 1) / per_grp + (n - nbig - ngrp + pack - 1) / pack;
         blocks = std::max(1, std::min(per_cu * cus, (chunks + wpb - 1) / wpb));
@@ -443,7 +444,8 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         return SIMINF_E_ARG;
     }
     if (m->opt.pipeline < 0 || m->opt.pipeline > 2 || m->opt.mode < 0 || m->opt.mode > 2 || m->opt.wait_ms < 0 ||
-        m->opt.lattice < 0 || m->opt.lattice > 2 || m->opt.graph < 0 || m->opt.graph > 1) {
+        m->opt.lattice < 0 || m->opt.lattice > 2 || m->opt.graph < 0 || m->opt.graph > 1 || m->opt.solver < 0 ||
+        m->opt.solver > 1) {
         set_create_error(m, SIMINF_E_ARG, -1, -1);
         return SIMINF_E_ARG;
     }
@@ -979,6 +981,12 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         p.ctrl = m->d_ctrl;
         p.rp = m->d_rp;
         p.group = (int)gi;
+        p.solver = m->opt.solver;
+        p.nt = g.shape.nt;
+        if (p.solver == 1 &&
+            (alloc_device(m->owned, (size_t)p.nt * n, &p.aem_T) || alloc_device(m->owned, (size_t)p.nt * n, &p.aem_P) ||
+             alloc_device(m->owned, (size_t)p.nt * n, &p.aem_K)))
+            return hip_fail(m);
         p.coupled = coupled ? 1 : 0;
         if (coupled) {
             int32_t *d_coff, *d_cfend, *d_cidx;
@@ -1001,7 +1009,7 @@ int create_impl(const siminf_spec* specs, int nspecs, const int32_t* reps, const
         }
         g.node_run = node_run;
         int lq = 0;
-        if (g.n_e2 == 0 && !coupled && !is_generated(g.model)) {
+        if (g.n_e2 == 0 && !coupled && !is_generated(g.model) && m->opt.solver == 0) {
             // the lane-queue chunk table: at most one chunk per run and per 64 nodes more
             g.chunk_cap = (int)grp_runs.size() + n / 64 + 1;
             if (alloc_device(m->owned, (size_t)g.chunk_cap, &g.d_chunks)) return hip_fail(m);
@@ -1429,7 +1437,8 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
     // the lane queue (models without external transfers), at three block
     // sizes and two chunk sizes, unless an option fixes the lane layout
     bool free_only = true;
-    for (const Group& g : m->groups) free_only = free_only && g.n_e2 == 0 && !g.p.coupled && !is_generated(g.model);
+    for (const Group& g : m->groups)
+        free_only = free_only && g.n_e2 == 0 && !g.p.coupled && !is_generated(g.model) && g.p.solver == 0;
     const bool shaped = m->opt.lanes != 0 || m->opt.wide != 0 || m->opt.group != 0 || m->opt.pack != 0;
     if (free_only && m->opt.lane_queue != 2 && (m->opt.lane_queue == 1 || !shaped)) {
         const int ch = m->opt.chunk > 0 ? m->opt.chunk : 512;

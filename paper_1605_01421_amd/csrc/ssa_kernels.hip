@@ -924,19 +924,150 @@ __device__ __forceinline__ void group_day(const KParams& p, Node<M>& s, bool liv
     day_events<M, false>(p, s, b, T, stream, cur, cend, nrec, wbase, dead, t, counter);
 }
 
+// ---------------------------------------------------------------------------
+// the all events method (section 3.4, 'aem')
+// ---------------------------------------------------------------------------
+// Every transition channel j of a node fires when its integrated rate T_j
+// reaches P_j, the running sum of unit exponentials from the channel's own
+// stream (Philox block (k, j, node, stream | 2 << 24), the k-th exponential
+// from the block's first two words).  The state per node and channel
+// carries over from day to day; the direct method needs none.
+template <class M, bool ON>
+struct AemState {};
+template <class M>
+struct AemState<M, true> {
+    double T[M::NT], P[M::NT];
+    uint32_t K[M::NT];
+};
+
+__device__ __forceinline__ double aem_exp(uint64_t seed, uint32_t k, uint32_t j, uint32_t node, uint32_t stream) {
+    const Block4 r = philox10((uint32_t)seed, (uint32_t)(seed >> 32), k, j, node, (stream & 0xFFFFFFu) | (2u << 24));
+    return -series_log(open_uniform(r.x, r.y));
+}
+
+template <class M>
+__device__ __forceinline__ double rate_at(int j, const Node<M>& s) {
+    if constexpr (M::GENERATED)
+        return M::rate(j, s.u, s.v, s.ld, s.gd);
+    else
+        return j == 0 ? M::template rate<0>(s.u, s.v, s.ld, s.gd) : M::template rate<1>(s.u, s.v, s.ld, s.gd);
+}
+
+template <class M>
+__device__ __forceinline__ void aem_load(const KParams& p, int k, AemState<M, true>& a) {
+#pragma unroll
+    for (int j = 0; j < M::NT; ++j) {
+        a.T[j] = p.aem_T[(size_t)j * p.n + k];
+        a.P[j] = p.aem_P[(size_t)j * p.n + k];
+        a.K[j] = p.aem_K[(size_t)j * p.n + k];
+    }
+}
+
+template <class M>
+__device__ __forceinline__ void aem_store(const KParams& p, int k, const AemState<M, true>& a) {
+#pragma unroll
+    for (int j = 0; j < M::NT; ++j) {
+        p.aem_T[(size_t)j * p.n + k] = a.T[j];
+        p.aem_P[(size_t)j * p.n + k] = a.P[j];
+        p.aem_K[(size_t)j * p.n + k] = a.K[j];
+    }
+}
+
+// One node from t to the day boundary T: the channel with the least
+// (P_j - T_j)/w_j fires (the lowest j on a tie) unless that time crosses T;
+// the other channels' integrals advance by w tau, the fired one's becomes
+// P_j and P_j takes the channel's next exponential; at the boundary every
+// integral advances by w (T - t).  The same checks as the direct method:
+// the step limit before each step, a negative compartment after a
+// transition, bad rates.  Channel arrays are indexed through unrolled
+// selects, so they stay in registers.
+template <class M>
+__device__ __forceinline__ int ssa_aem(const KParams& p, Node<M>& s, AemState<M, true>& a, double t, double T,
+                                       uint32_t node, uint32_t stream, unsigned long long& transitions,
+                                       unsigned long long& draws) {
+    double w[M::NT];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < M::NT; ++j) {
+        w[j] = rate_at<M>(j, s);
+        bad = bad || !rate_ok(w[j]);
+    }
+    if (bad) return E_BAD_RATE;
+    for (uint32_t k = 0;; ++k) {
+        int n = -1;
+        double best = 0.0;
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j) {
+            const double tau = (a.P[j] - a.T[j]) / w[j];
+            const bool take = w[j] > 0.0 && (n < 0 || tau < best);
+            best = take ? tau : best;
+            n = take ? j : n;
+        }
+        if (n < 0) return 0;
+        if (k == STEP_LIMIT) return E_STEP_LIMIT;
+        draws += 1;
+        const double tn = t + best;
+        if (tn >= T) {
+            const double rest = T - t;
+#pragma unroll
+            for (int j = 0; j < M::NT; ++j) a.T[j] = a.T[j] + w[j] * rest;
+            return 0;
+        }
+        double pn = 0.0;
+        uint32_t kn = 0;
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j) {
+            pn = j == n ? a.P[j] : pn;
+            kn = j == n ? a.K[j] : kn;
+        }
+        const double pnext = pn + aem_exp(p.seed, kn, (uint32_t)n, node, stream);
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j) {
+            const bool f = j == n;
+            a.T[j] = f ? a.P[j] : a.T[j] + w[j] * best;
+            a.P[j] = f ? pnext : a.P[j];
+            a.K[j] = f ? a.K[j] + 1u : a.K[j];
+        }
+        t = tn;
+        uint32_t g;
+        if constexpr (M::GENERATED) {
+            M::apply(n, s.u);
+            g = M::deps(n);
+        } else {
+#pragma unroll
+            for (int c = 0; c < M::NC; ++c) s.u[c] += n ? p.S[c + M::NC] : p.S[c];
+            g = n ? p.Gmask[1] : p.Gmask[0];
+        }
+        transitions += 1;
+        bool neg = false;
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) neg = neg || s.u[c] < 0;
+        if (neg) return E_NEG_STATE;
+#pragma unroll
+        for (int j = 0; j < M::NT; ++j)
+            if ((g >> j) & 1u) {
+                w[j] = rate_at<M>(j, s);
+                bad = bad || !rate_ok(w[j]);
+            }
+        if (bad) return E_BAD_RATE;
+    }
+}
+
 // SSA to day boundary b, then the node's E1 events with time <= T.  With
 // wide, the whole wavefront carries the node (the lattice walk, or the plain
 // chain when G does not mark both rates); event tallies are then kept by
-// lane 0 only.
-template <class M, bool PIPE>
+// lane 0 only.  With AEM, the all events method on one lane.
+template <class M, bool PIPE, bool AEM = false>
 __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, int64_t day, uint32_t node,
                                            uint32_t stream, int64_t ord, int& cur, int cend, int4& nrec, int& wbase,
-                                           bool& dead, Tally& t, bool wide) {
+                                           bool& dead, Tally& t, bool wide, AemState<M, AEM>& a) {
     const double T = (double)day;
     const double t0 = b == 0 ? p.t0 : T - 1.0;
     const uint32_t dw = (uint32_t)(int32_t)day;
     int rc = 0;
-    if constexpr (M::GENERATED)
+    if constexpr (AEM)
+        rc = ssa_aem<M>(p, s, a, t0, T, node, stream, t.tr, t.dr);
+    else if constexpr (M::GENERATED)
         rc = ssa_to_boundary<M, PIPE>(p, s, t0, T, dw, node, stream, t.tr, t.dr);  // never wide
     else
         rc = !wide       ? ssa_to_boundary<M, PIPE>(p, s, t0, T, dw, node, stream, t.tr, t.dr)
@@ -957,7 +1088,7 @@ __device__ __forceinline__ void ssa_and_e1(const KParams& p, Node<M>& s, int b, 
 // ---------------------------------------------------------------------------
 // free-running kernel (no external transfers)
 // ---------------------------------------------------------------------------
-template <class M, bool PIPE, bool GRP>
+template <class M, bool PIPE, bool GRP, bool AEM = false>
 __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
     KParams p = pa;
     p.seed = pa.rp->seed;
@@ -985,7 +1116,11 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
         int64_t ord = 0;
         int4 nrec = make_int4(0, 0, 0, 0);
         int wbase = 0;
-        if (active) load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec, wide, wbase);
+        AemState<M, AEM> a{};
+        if (active) {
+            load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec, wide, wbase);
+            if constexpr (AEM) aem_load<M>(p, k, a);
+        }
 
         bool dead = false;
         uint64_t key_raw = 0;  // error key, refreshed every 8 days and read 8 days later
@@ -998,7 +1133,8 @@ __global__ void __launch_bounds__(256) free_kernel(KParams pa) {
             const int64_t day = p.T1 + b;
             if (grp) group_day<M>(p, s, active && !dead, b, day, node, stream, ord, cur, cend, nrec, dead, t, owner);
             if (active && !dead) {
-                if (!grp) ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, wbase, dead, t, wide);
+                if (!grp)
+                    ssa_and_e1<M, PIPE, AEM>(p, s, b, day, node, stream, ord, cur, cend, nrec, wbase, dead, t, wide, a);
                 if (!dead && !M::pts(s.v, s.u, s.ld, s.gd, day)) {
                     if (owner) raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
                     dead = true;
@@ -1456,7 +1592,7 @@ __device__ __forceinline__ double coupled_sum(const KParams& p, const Node<M>& s
     return c;
 }
 
-template <class M, bool PIPE, bool GRP>
+template <class M, bool PIPE, bool GRP, bool AEM = false>
 __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     KParams p = pa;
     p.seed = pa.rp->seed;
@@ -1483,8 +1619,10 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
     int64_t ord = 0;
     int4 nrec = make_int4(0, 0, 0, 0), item = make_int4(0, NO_STEP, 0, 0), trec = make_int4(0, 0, 0, 0);
     int wbase = 0;
+    AemState<M, AEM> a{};
     if (active) {
         load_node<M>(p, k, s, run, node, stream, ord, cur, cend, nrec, wide, wbase);
+        if constexpr (AEM) aem_load<M>(p, k, a);
         tcur = p.e2n_off[k];
         tend = p.e2n_off[k + 1];
         if (tcur < tend) {
@@ -1505,7 +1643,7 @@ __global__ void __launch_bounds__(256) flow_kernel(KParams pa) {
         if (grp)
             group_day<M>(p, s, active && !dead, b, day, node, stream, ord, cur, cend, nrec, dead, t, owner);
         else if (active && !dead)
-            ssa_and_e1<M, PIPE>(p, s, b, day, node, stream, ord, cur, cend, nrec, wbase, dead, t, wide);
+            ssa_and_e1<M, PIPE, AEM>(p, s, b, day, node, stream, ord, cur, cend, nrec, wbase, dead, t, wide, a);
 
         // this step's external transfers of the node, in key order.  The loop
         // is uniform over the wavefront and every lane that can move on does:
@@ -1624,7 +1762,7 @@ __device__ __forceinline__ void load_live(const KParams& p, Node<M>& s, int k) {
     for (int c = 0; c < M::NV; ++c) s.v[c] = p.v[(size_t)c * p.n + k];
 }
 
-template <class M, bool PIPE>
+template <class M, bool PIPE, bool AEM = false>
 __global__ void __launch_bounds__(256) sync_kernel(KParams pa) {
     KParams p = pa;
     p.seed = pa.rp->seed;
@@ -1654,8 +1792,11 @@ __global__ void __launch_bounds__(256) sync_kernel(KParams pa) {
                 const int cend = p.e1_off[k + 1];
                 int4 nrec = cur < cend ? p.e1.rec[cur] : make_int4(0, 0, 0, 0);
                 int wbase = cur;
-                ssa_and_e1<M, PIPE>(p, s, b, day, (uint32_t)p.node_idx[k], stream, ord, cur, cend, nrec, wbase, dead,
-                                    t, false);
+                AemState<M, AEM> a{};
+                if constexpr (AEM) aem_load<M>(p, k, a);
+                ssa_and_e1<M, PIPE, AEM>(p, s, b, day, (uint32_t)p.node_idx[k], stream, ord, cur, cend, nrec, wbase,
+                                         dead, t, false, a);
+                if constexpr (AEM) aem_store<M>(p, k, a);
                 p.e1_cur[k] = cur;
                 if (!e2day && !dead && !M::pts(s.v, s.u, s.ld, s.gd, day))
                     raise_error(p.ctrl, b, PH_PTS, ord, E_PTS);
@@ -1749,6 +1890,18 @@ __global__ void init_kernel(KParams p, int nc, int nv, int first_rec, int reset_
         for (int e = gtid; e < p.n_e2; e += nthreads) p.mail[e] = 0ull;
     if (p.coupled)
         for (int i = gtid; i < 2 * p.n; i += nthreads) p.cpl_post[i].day = -1;
+    if (p.solver == 1) {
+        // the all events method: integrals 0, each channel's first level its
+        // first exponential
+        const uint64_t seed = p.rp->seed;
+        for (int i = gtid; i < p.nt * p.n; i += nthreads) {
+            const int j = i / p.n, k = i % p.n;
+            const uint32_t stream = p.rp->stream_base + (uint32_t)p.node_run[k];
+            p.aem_T[i] = 0.0;
+            p.aem_P[i] = aem_exp(seed, 0u, (uint32_t)j, (uint32_t)p.node_idx[k], stream);
+            p.aem_K[i] = 1u;
+        }
+    }
     for (int k = gtid; k < p.n; k += nthreads) {
         if (p.mode == MODE_BARRIER) {
             for (int c = 0; c < nc; ++c) p.u[(size_t)c * p.n + k] = p.u0[(size_t)c * p.n + k];
@@ -1851,21 +2004,29 @@ const void* kernel_for(int mode, bool grp) {
 }
 
 template <class M>
-const void* kernel_for(int mode, int pipeline, bool grp, bool lq) {
+const void* kernel_for(int mode, int pipeline, bool grp, bool lq, bool aem) {
+    if (aem) {
+        // the all events method: one lane per node
+        if (grp || lq) return nullptr;
+        if (mode == MODE_FLOW) return (const void*)flow_kernel<M, false, false, true>;
+        if (mode == MODE_BARRIER) return (const void*)sync_kernel<M, false, true>;
+        return (const void*)free_kernel<M, false, false, true>;
+    }
     if (mode == MODE_FREE && lq) return pipeline ? (const void*)lane_kernel<M, true> : (const void*)lane_kernel<M, false>;
     return pipeline ? kernel_for<M, true>(mode, grp) : kernel_for<M, false>(mode, grp);
 }
 
-const void* model_kernel(int model, int mode, int pipeline, bool grp, bool lq) {
+const void* model_kernel(int model, int mode, int pipeline, bool grp, bool lq, bool aem) {
     switch (model) {
-        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline, grp, lq);
-        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline, grp, lq);
-        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline, grp, lq);
-        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline, grp, lq);
-        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline, grp, lq);
+        case M_SIR: return kernel_for<ModelSIR>(mode, pipeline, grp, lq, aem);
+        case M_SIS: return kernel_for<ModelSIS>(mode, pipeline, grp, lq, aem);
+        case M_SISE: return kernel_for<ModelSISe>(mode, pipeline, grp, lq, aem);
+        case M_BIRTH_DEATH: return kernel_for<ModelBirthDeath>(mode, pipeline, grp, lq, aem);
+        case M_IMMIGRATION_DEATH: return kernel_for<ModelImmigrationDeath>(mode, pipeline, grp, lq, aem);
         case M_SISE_SP:
             // the coupled post-time step exists in the dataflow kernel only
             if (mode != MODE_FLOW || lq) return nullptr;
+            if (aem) return grp ? nullptr : (const void*)flow_kernel<ModelSISeSp, false, false, true>;
             if (pipeline)
                 return grp ? (const void*)flow_kernel<ModelSISeSp, true, true>
                            : (const void*)flow_kernel<ModelSISeSp, true, false>;
@@ -1891,7 +2052,7 @@ hipError_t launch_init(const KParams& p, int nc, int nv, int first_rec, bool res
 
 hipError_t launch_group(int model, const KParams& p, int block, int blocks, size_t shmem, hipStream_t st) {
     if (model >= SIMINF_GEN_FIRST) return generated_launch(model, p, block, blocks, shmem, st);
-    const void* fn = model_kernel(model, p.mode, p.pipeline, p.ngrp > 0, p.lane_queue != 0);
+    const void* fn = model_kernel(model, p.mode, p.pipeline, p.ngrp > 0, p.lane_queue != 0, p.solver == 1);
     if (!fn) return hipErrorInvalidValue;
     KParams arg = p;
     void* args[] = {&arg};
@@ -1899,9 +2060,11 @@ hipError_t launch_group(int model, const KParams& p, int block, int blocks, size
     return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(block), args, (unsigned)shmem, st);
 }
 
-int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem, bool lane_queue) {
-    if (model >= SIMINF_GEN_FIRST) return grp || lane_queue ? 0 : generated_blocks_per_cu(model, mode, pipeline, block, shmem);
-    const void* fn = model_kernel(model, mode, pipeline, grp, lane_queue);
+int max_blocks_per_cu(int model, int mode, int pipeline, bool grp, int block, size_t shmem, bool lane_queue,
+                      bool aem) {
+    if (model >= SIMINF_GEN_FIRST)
+        return grp || lane_queue ? 0 : generated_blocks_per_cu(model, mode, pipeline, block, shmem, aem);
+    const void* fn = model_kernel(model, mode, pipeline, grp, lane_queue, aem);
     int n = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, shmem) != hipSuccess) return 0;
     return n;

@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("pipeline", ctypes.c_int32), ("mode", ctypes.c_int32), ("wide", ctypes.c_int32),
                 ("lattice", ctypes.c_int32), ("wait_ms", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("pack", ctypes.c_int32), ("group", ctypes.c_int32), ("lane_queue", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("batch", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("batch", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
 # exported entry points: name -> (restype, argtypes)
@@ -275,12 +275,12 @@ class Model:
     def __init__(self, spec, record: int = RECORD_FULL, block: int = 0, order: int = 0,
                  lanes: int = 0, max_blocks: int = 0, pipeline: int = 0, mode: int = 0, wide: int = 0,
                  lattice: int = 0, wait_ms: int = 0, graph: int = 0, pack: int = 0, group: int = 0,
-                 lane_queue: int = 0, chunk: int = 0, batch: int = 0):
+                 lane_queue: int = 0, chunk: int = 0, batch: int = 0, solver: str = "ssm"):
         lib = load()
         self._lib = lib
         self._h = ctypes.c_void_p()
         opt = Options(record, block, order, lanes, max_blocks, pipeline, mode, wide, lattice, wait_ms, graph, pack,
-                      group, lane_queue, chunk, batch)
+                      group, lane_queue, chunk, batch, {"ssm": 0, "aem": 1}[solver])
         keep: list = []
         if isinstance(spec, (list, tuple)):
             specs = [s for s, _ in spec]
