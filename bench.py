@@ -47,7 +47,8 @@ OPS_PER_STEP = 260
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
-SSA_SOURCES = ("device_math.h", "internal.h", "models.h", "runtime.cpp", "ssa_kernels.hip")
+SOLVER = "ssm"  # the solver of the timed runs and of the CPU baseline (--solver)
+SSA_SOURCES = ("device_types.h", "device_math.h", "internal.h", "models.h", "runtime.cpp", "ssa_kernels.hip")
 
 
 def _progress(*a):
@@ -137,6 +138,8 @@ def build_workload(name):
         spec = W.sise_with_events()
     elif name == "sise-sp":
         spec = W.sise_sp_with_events()
+    elif name == "vaccination":
+        spec = W.vaccination_example(infected=16)
     elif name == "ensemble":
         sets = W.ensemble_sets(seed=3, n_sets=64, replicates=64)
         nodes = sum(s.spec.Nn for s in sets) * 64
@@ -146,9 +149,9 @@ def build_workload(name):
         return [(s.spec, 64) for s in sets], desc
     else:
         raise SystemExit(f"unknown workload {name}")
+    model = ("generated: " + "; ".join(spec.mparse["transitions"])) if spec.mparse else MODEL_NAMES[int(spec.model)]
     desc = {"workload": spec.name, "nodes": spec.Nn, "days": spec.n_days,
-            "scheduled_events": int(len(spec.events["time"])), "model": MODEL_NAMES[int(spec.model)],
-            "record": "U every day"}
+            "scheduled_events": int(len(spec.events["time"])), "model": model, "record": "U every day"}
     return spec, desc
 
 
@@ -170,7 +173,7 @@ def cpu_baseline_batch(batch, seed, seconds, gpu_sums):
         if t_total >= seconds:
             break
         t0 = time.perf_counter()
-        out = oracle.run(flat[r], seed, r, nthreads=threads)
+        out = oracle.run(flat[r], seed, r, nthreads=threads, solver=SOLVER)
         t_total += time.perf_counter() - t0
         sums = out["U"].astype("int64").sum(axis=1)
         parity = parity and out["status"] == 0 and bool((gpu_sums[r, :, :sums.shape[1]] == sums).all())
@@ -192,7 +195,7 @@ def cpu_baseline(spec, seed, seconds, gpu_counters):
     parity = None
     while t_total < seconds and runs < 2000:
         t0 = time.perf_counter()
-        r = oracle.run(spec, seed + runs, 0, nthreads=threads)
+        r = oracle.run(spec, seed + runs, 0, nthreads=threads, solver=SOLVER)
         t_total += time.perf_counter() - t0
         if runs == 0:
             parity = (r["transitions"], r["events"]) == (gpu_counters["transitions"], gpu_counters["events"])
@@ -270,7 +273,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ensemble",
-                    help="ensemble (default: 64 sets x 64 replicates), sir-events, sise-events, sise-sp, sir-plain, mlp")
+                    help="ensemble (default: 64 sets x 64 replicates), sir-events, sise-events, sise-sp, vaccination "
+                         "(a model given as transition strings), sir-plain, mlp")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per node: 0 auto, 1, 64")
@@ -287,11 +291,15 @@ def main():
                     help="replay the run from a captured HIP graph: 1 on, 0 off, -1 on for batches without transfers")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (launch shape from heuristics)")
+    ap.add_argument("--solver", default="ssm", choices=["ssm", "aem"],
+                    help="ssm: the split-step direct method (default); aem: the all events method")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy a 256 MiB device buffer once (known-size reference "
                          "kernel for hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
+    global SOLVER
+    SOLVER = args.solver
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the simulation of one run "
               "is not sharded across GPUs in this build", file=sys.stderr)
@@ -312,7 +320,7 @@ def main():
     model = siminf.Model(spec, record=siminf.RECORD_SUMS if batch else siminf.RECORD_FULL, block=args.block,
                          order=args.order, lanes=args.lanes, wide=args.wide, pipeline=args.pipeline,
                          pack=args.pack, graph=graph, group=args.group, lane_queue=args.lane_queue,
-                         chunk=args.chunk, batch=args.batch)
+                         chunk=args.chunk, batch=args.batch, solver=args.solver)
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
@@ -379,7 +387,7 @@ def main():
                        kernel=["free-running", "grid-barrier", "dataflow", "lane-queue"][info["mode"]],
                        chunk=info["chunk"], batch=info["batch"],
                        wide_nodes=info["wide"], pipeline=info["pipeline"], pack=info["pack"],
-                       group_nodes=info["group"], graph=graph),
+                       group_nodes=info["group"], graph=graph, solver=args.solver),
         "transitions_per_s": transitions / wall,
         "events_per_step": events / args.steps,
         "kernel_ms_mean": mean_kernel_s * 1e3,
