@@ -48,7 +48,8 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
 SOLVER = "ssm"  # the solver of the timed runs and of the CPU baseline (--solver)
-SSA_SOURCES = ("device_types.h", "device_math.h", "internal.h", "models.h", "runtime.cpp", "ssa_kernels.hip")
+SSA_SOURCES = ("device_types.h", "device_math.h", "internal.h", "models.h", "runtime.cpp", "ssa_kernels.hip",
+               "generated.cpp")
 
 
 def _progress(*a):
@@ -109,7 +110,7 @@ def algorithmic_bytes(spec, record_sums: bool) -> float:
     runs = spec if isinstance(spec, list) else [(spec, 1)]
     total = 0.0
     for sp, reps in runs:
-        nn, nc = sp.Nn, int(np.asarray(sp.S).shape[0])
+        nn, nc = sp.Nn, sp.Nc
         nv = int(np.asarray(sp.v0).reshape(nn, -1).shape[1]) if nn else 0
         nld = int(np.asarray(sp.ldata).reshape(nn, -1).shape[1]) if nn else 0
         ev = np.asarray(sp.events["event"])
@@ -324,11 +325,14 @@ def main():
     seed0 = 20240000
     tuned_ms = None
     if not args.no_tune:
-        # one plain run first: long runs are tuned on one repeat per shape
+        # one plain run first: long runs are tuned on one repeat per shape,
+        # short ones on the mean over four seeds (a shape that is fast on
+        # most seeds but slow on some, e.g. with the heaviest nodes on one
+        # lane, is not taken)
         model.run(seed0 - 2000)
         assert model.wait() == 0, model.error_info()
         probe_ms = model.timing()["kernel_ms"]
-        repeats = 1 if probe_ms > 500 else 2
+        repeats = 1 if probe_ms > 500 else 2 if probe_ms > 100 else 4
         if probe_ms > 500:
             os.environ["SIMINF_AUTOTUNE_LOG"] = "1"  # a line per shape: long tunes keep printing
         _progress(f"autotuning ({probe_ms:.1f} ms per run, {repeats} repeat(s) per shape)")
@@ -369,6 +373,8 @@ def main():
     achieved = draws_per_launch * OPS_PER_STEP / mean_kernel_s
     info = model.launch_info()
     kernel_name = ["free_kernel", "sync_kernel", "flow_kernel", "lane_kernel"][info["mode"]]
+    if args.solver == "aem":
+        kernel_name += "_aem"  # the all events method's instantiation
     traffic_bytes, traffic_launch = measured_traffic_at(kernel_name, desc["workload"])
     out = {
         "metric": METRIC,

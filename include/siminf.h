@@ -233,7 +233,12 @@ typedef struct {
                           covers the short init kernel.  0 (default): plain
                           launches. */
     int32_t pack;      /* nodes in a wavefront that gives each node one lane: 64,
-                          32, 16, 8 or 4 (the remaining lanes idle); 0 = 64.  Fewer
+                          32, 16, 8 or 4 (the remaining lanes idle); 0 auto: 64,
+                          unless the device has more CUs than wavefronts, then
+                          the largest packing that gives each SIMD a wavefront
+                          (at least 16 with SISe_sp coupling; 4 if none does),
+                          raised again where the dataflow kernel cannot hold
+                          every wavefront.  Fewer
                           nodes per wavefront shorten a latency-bound run (each
                           wavefront's day ends with its slowest node, and an
                           external transfer holds back only the destination's
@@ -402,8 +407,8 @@ int siminf_launch_info(const siminf_model *m, int32_t out[12]);
  * (threads per block 64/128/256; no wavefront-wide nodes, or those whose
  * expected work exceeds 1/4, 1/16 or 1/64 of the heaviest node's;
  * pipelining on/off), on hip_stream with seeds seed, seed+1, ..., and keeps
- * the shape with the smallest lower-median SSA-kernel time (the faster of
- * two repeats; written to *best_ms if not NULL).  With pack = 0 and fewer
+ * the shape with the smallest mean SSA-kernel time over the repeats
+ * (written to *best_ms if not NULL).  With pack = 0 and fewer
  * nodes than the device has SIMDs times 64, it then tries 32, 16, 8 and 4
  * nodes per wavefront on the best shape and, if one of those wins, the four
  * wide-node choices again with it; then (with group = 0) groups of lanes for

@@ -358,10 +358,24 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
     const int cus = device_cus(m);
     if (cus <= 0) return SIMINF_E_DEVICE;
     nbig = std::max(0, std::min(nbig, n));
-    if (pack != 4 && pack != 8 && pack != 16 && pack != 32) pack = WAVE;
     // nodes on a group of lanes: only where the lattice walk applies
     const int per_grp = WAVE / GROUP_LANES;
     ngrp = p.lattice ? std::max(0, std::min(ngrp, n - nbig)) : 0;
+    // pack 0 (auto): 64 nodes to a wavefront, unless that leaves CUs without a
+    // wavefront; then the largest packing that gives every SIMD one (at least
+    // 16 nodes to a wavefront in the coupled kernel, whose posts every
+    // wavefront polls), else the smallest allowed
+    const bool auto_pack = pack == 0;
+    if (auto_pack) {
+        const long long major = (long long)nbig + (ngrp + per_grp - 1) / per_grp;
+        const long long rest = n - nbig - ngrp;
+        pack = WAVE;
+        if (major + (rest + WAVE - 1) / WAVE < cus) {
+            const int smallest = p.coupled ? 16 : 4;
+            while (pack > smallest && major + (rest + pack - 1) / pack < (long long)cus * 4) pack /= 2;
+        }
+    }
+    if (pack != 4 && pack != 8 && pack != 16 && pack != 32) pack = WAVE;
     // pipelining pays where lanes are scarce (latency-bound runs); with many
     // waves per SIMD the extra, unused last draw of each node-day only costs
     const int simd_lanes = cus * 4 * WAVE;
@@ -378,7 +392,9 @@ int configure(siminf_model* m, Group& g, int block, int nbig, int pipeline, int 
             auto need = [&](int k, int gn) {
                 return (k + (gn + per_grp - 1) / per_grp + (n - k - gn + pack - 1) / pack + wpb - 1) / wpb;
             };
-            // every wavefront must be resident: drop the groups first, then halve the wide nodes
+            // every wavefront must be resident: undo an automatic packing
+            // first, then drop the groups, then halve the wide nodes
+            while (auto_pack && pack < WAVE && per_cu > 0 && need(nb, ng) > per_cu * cus) pack *= 2;
             if (ng > 0 && (per_cu <= 0 || need(nb, ng) > per_cu * cus)) {
                 ng = 0;
                 per_cu = max_blocks_per_cu(g.model, MODE_FLOW, p.pipeline, false, block, 0, false, aem);
@@ -1408,8 +1424,10 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
         if (m->opt.group != 0) return m->opt.group < 0 ? g.n : (int)m->opt.group;
         return m->opt.order == 1 ? 0 : default_group(g, nb, gdiv);
     };
-    // lower-median SSA-kernel time of one candidate over `repeats` runs, or a
-    // negative value if it cannot be launched
+    // mean SSA-kernel time of one candidate over `repeats` runs (seeds seed,
+    // seed + 1, ...), or a negative value if it cannot be launched: a shape
+    // that is fast on most seeds but much slower on some (the heaviest nodes
+    // on one lane) is judged by its average
     auto measure = [&](const Cand& c) -> double {
         for (Group& g : m->groups) {
             const int nb = default_wide(m, g, c.wide_div);
@@ -1425,8 +1443,9 @@ int siminf_autotune(siminf_model* m, uint64_t seed, int32_t repeats, void* hip_s
                 return -1.0;
             t.push_back(ms[0]);
         }
-        std::sort(t.begin(), t.end());
-        return t[(t.size() - 1) / 2];  // lower median: the faster of two repeats
+        double sum = 0.0;
+        for (double x : t) sum += x;
+        return sum / (double)t.size();
     };
     const int pack0 = m->opt.pack ? m->opt.pack : WAVE;
     std::vector<Cand> cands;

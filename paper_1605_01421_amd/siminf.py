@@ -313,8 +313,9 @@ class Model:
             self._lib.siminf_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be gone at exit)
+        if _finalizing():
             return  # the process is ending: the device memory goes with it
         try:
             self.close()
@@ -477,8 +478,9 @@ class MLP:
             self._lib.siminf_mlp_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be gone at exit)
+        if _finalizing():
             return  # the process is ending: the device memory goes with it
         try:
             self.close()

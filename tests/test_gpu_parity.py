@@ -436,6 +436,48 @@ def test_packed_wavefronts_batch(lib, pack, group):
         assert np.array_equal(sums[r, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), r
 
 
+def _expected_auto_pack(info, Nn, cus, smallest):
+    """The automatic packing rule, restated from the option's documentation."""
+    major = info["wide"] + -(-info["group"] // 8)
+    rest = Nn - info["wide"] - info["group"]
+    pack = 64
+    if major + -(-rest // 64) < cus:
+        while pack > smallest and major + -(-rest // pack) < 4 * cus:
+            pack //= 2
+    return pack
+
+
+@pytest.mark.parametrize("case", ["transfers-600", "generated-800", "aem-2000"])
+def test_automatic_packing(lib, case):
+    """With no launch option a model with fewer 64-node wavefronts than the
+    device has CUs packs fewer nodes to a wavefront; the results stay the
+    oracle's."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    solver = "ssm"
+    if case == "transfers-600":
+        spec = W.sir_with_events(seed=8, Nn=600, days=60)
+    elif case == "generated-800":
+        spec = W.vaccination_example(seed=4, Nn=800, days=60, infected=20)
+    else:
+        spec = W.sir_with_events(seed=9, Nn=2000, days=40)
+        solver = "aem"
+    m = lib.Model(spec, solver=solver)
+    info = m.launch_info()
+    _say("automatic packing", case, info, "CUs", cus)
+    assert info["pack"] == _expected_auto_pack(info, spec.Nn, cus, 4)
+    one_lane = spec.Nn - info["wide"] - info["group"]
+    if case != "transfers-600":
+        assert one_lane == spec.Nn  # one lane per node: no wide or grouped nodes
+    if one_lane > 0 and info["wide"] + -(-info["group"] // 8) + -(-one_lane // 64) < cus:
+        assert info["pack"] < 64
+    m.run(23, 6)
+    assert m.wait() == 0
+    import oracle
+    ref = oracle.run(spec, 23, 6, nthreads=NTHREADS, solver=solver)
+    _compare(m, ref, what=case)
+
+
 def test_split_run_equals_full_run(lib):
     """Draws are keyed by the absolute day: running [0, 40] and then
     [40, 90] from the saved state equals one run over [0, 90] on the GPU

@@ -127,6 +127,25 @@ def test_sise_sp_launch_shapes(lib, opts):
     _counters_match(m, ref)
 
 
+def test_sise_sp_automatic_packing(lib):
+    """With no packing option the coupled kernel packs at least 16 nodes to a
+    wavefront (every node on one lane: fewer 64-node wavefronts than CUs
+    here); bits unchanged."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    spec = W.sise_sp_with_events(seed=5, Nn=400, days=150)
+    ref = _oracle(spec, 17, 2)
+    m = lib.Model(spec, lanes=1)
+    info = m.launch_info()
+    _say("automatic packing", info, "CUs", cus)
+    if cus >= 8:
+        assert info["pack"] == 16
+    m.run(17, 2)
+    assert m.wait() == 0
+    _same(m, ref, what="automatic packing")
+    _counters_match(m, ref)
+
+
 def test_sise_sp_replicates(lib):
     """Replicates of one coupled model in one launch: each couples only its
     own nodes."""
