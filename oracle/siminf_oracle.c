@@ -174,11 +174,15 @@ double oracle_uniform(uint32_t a, uint32_t b) {
  *   x = m * 2^e with m in [1,2) taken from the bit pattern;
  *   if m > sqrt(2): m = m/2, e = e+1        (so m in (sqrt(1/2), sqrt(2)])
  *   s = (m-1)/(m+1);  z = s*s
- *   ln m = 2*atanh(s) = 2s * sum_{k=0..11} z^k/(2k+1)   (Horner in z)
- *   ln x = e*LN2_HI + (e*LN2_LO + ln m)
+ *   ln m = 2*atanh(s) = 2s * sum_{k=0..11} z^k/(2k+1)
+ *          (Horner in z, each step p*z + c one fused multiply-add)
+ *   ln x = fma(e, LN2_HI, fma(e, LN2_LO, ln m))
  * with LN2_HI/LN2_LO the classic two-part split of ln 2 (upper part with
  * 32 trailing zero bits so e*LN2_HI is exact).  Series truncation < 2^-60
- * relative since |s| <= 0.1716. */
+ * relative since |s| <= 0.1716.  fma() is the C library's correctly rounded
+ * fused multiply-add; the clone for processors with FMA instructions
+ * computes the same values. */
+__attribute__((target_clones("fma", "default")))
 double oracle_plog(double x) {
     const double SQRT2 = 0x1.6a09e667f3bcdp+0;
     const double LN2_HI = 0x1.62e42feep-1;
@@ -197,20 +201,20 @@ double oracle_plog(double x) {
     double s = f / (m + 1.0);
     double z = s * s;
     double p = 1.0 / 23.0;
-    p = p * z + 1.0 / 21.0;
-    p = p * z + 1.0 / 19.0;
-    p = p * z + 1.0 / 17.0;
-    p = p * z + 1.0 / 15.0;
-    p = p * z + 1.0 / 13.0;
-    p = p * z + 1.0 / 11.0;
-    p = p * z + 1.0 / 9.0;
-    p = p * z + 1.0 / 7.0;
-    p = p * z + 1.0 / 5.0;
-    p = p * z + 1.0 / 3.0;
-    p = p * z + 1.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
     double lnm = (s + s) * p;
     double de = (double)e;
-    return de * LN2_HI + (de * LN2_LO + lnm);
+    return fma(de, LN2_HI, fma(de, LN2_LO, lnm));
 }
 
 /* ---- RNG keying --------------------------------------------------------

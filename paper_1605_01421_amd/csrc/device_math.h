@@ -32,16 +32,33 @@ __device__ __forceinline__ Block4 philox10(uint32_t k0, uint32_t k1, uint32_t x0
     return {x0, x1, x2, x3};
 }
 
-// (0,1) uniform from 52 random bits: hi word's 32 bits above lo word's top 20,
-// centred in its cell, so the value is exact and never 0 or 1.
+// (0,1) uniform from 52 random bits k (hi word's 32 bits above lo word's top
+// 20), centred in its cell: (k + 1/2) 2^-52, exact, never 0 or 1.  Computed
+// as the double with exponent 0 and fraction k, 1 + k 2^-52, minus the
+// largest double below 1, 1 - 2^-53: by Sterbenz's lemma the difference is
+// exact, so this is the value above without an integer conversion.
 __device__ __forceinline__ double open_uniform(uint32_t hi, uint32_t lo) {
-    const uint64_t bits52 = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
-    return ((double)bits52 + 0.5) * 0x1p-52;
+    const uint32_t frac_lo = (hi << 20) | (lo >> 12);
+    const uint32_t frac_hi = (hi >> 12) | 0x3ff00000u;
+    const double one_plus = __longlong_as_double((long long)(((uint64_t)frac_hi << 32) | frac_lo));
+    return one_plus - 0x1.fffffffffffffp-1;
+}
+
+// A constant for the addend of a fused multiply-add, in a scalar register
+// pair at its point of use: otherwise the compiler keeps the series'
+// coefficients in vector registers across the draw loop (20 of them) and adds
+// a vector move before every multiply-add.  The empty statement emits no
+// instruction.
+__device__ __forceinline__ double in_sgpr(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
 }
 
 // Natural log of a normal x in (0, 1]: x = m 2^e with m in (sqrt(1/2), sqrt(2)],
 // ln m = 2 atanh(s), s = (m-1)/(m+1), as s * (2 + 2z/3 + ... + 2z^11/23),
-// z = s^2 (Horner); ln x = e ln2_hi + (e ln2_lo + ln m).
+// z = s^2, by Horner with one fused multiply-add (one rounding) per step;
+// ln x = e ln2_hi + (e ln2_lo + ln m), both as fused multiply-adds (the
+// first product is exact: ln2_hi has 32 trailing zero bits).
 __device__ __forceinline__ double series_log(double x) {
     const uint64_t ix = (uint64_t)__double_as_longlong(x);
     int ex = (int)((ix >> 52) & 0x7ff) - 1023;
@@ -54,20 +71,20 @@ __device__ __forceinline__ double series_log(double x) {
     const double z = s * s;
     // coefficients 1/(2k+1), k = 11 .. 0, each the correctly rounded quotient
     double h = 1.0 / 23.0;
-    h = h * z + 1.0 / 21.0;
-    h = h * z + 1.0 / 19.0;
-    h = h * z + 1.0 / 17.0;
-    h = h * z + 1.0 / 15.0;
-    h = h * z + 1.0 / 13.0;
-    h = h * z + 1.0 / 11.0;
-    h = h * z + 1.0 / 9.0;
-    h = h * z + 1.0 / 7.0;
-    h = h * z + 1.0 / 5.0;
-    h = h * z + 1.0 / 3.0;
-    h = h * z + 1.0;
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 21.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 19.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 17.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 15.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 13.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 11.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 9.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 7.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 5.0));
+    h = __builtin_fma(h, z, in_sgpr(1.0 / 3.0));
+    h = __builtin_fma(h, z, 1.0);
     const double lnm = (s + s) * h;
     const double fe = (double)ex;
-    return fe * 0x1.62e42feep-1 + (fe * 0x1.a39ef35793c76p-33 + lnm);
+    return __builtin_fma(fe, 0x1.62e42feep-1, __builtin_fma(fe, 0x1.a39ef35793c76p-33, lnm));
 }
 
 // Sequential 32-bit words of the Philox blocks (b, 0, id, stream | 1<<24),
