@@ -36,12 +36,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSA node-days/sec + transitions/sec on 1 MI355X; surrogate speedup at fixed error"
 
-# VALU lane-operations of one SSA step of the documented formula (full-rate
-# equivalents; 32x32->64 integer products count 4): Philox4x32-10 140,
-# two 52-bit uniforms 8, series logarithm 35 (13 of them fused multiply-adds),
-# waiting time and boundary test 14, inversion 5, state update 8, SIR rate
-# recomputation and checks 24, loop bookkeeping 7.
-OPS_PER_STEP = 241
+# VALU lane-operations of one SSA step: the 172 VALU instructions of the
+# compiled draw loop of the SISe lane-queue kernel (18 32x32->64 products, 56
+# integer and logic, 53 FP64, 45 selects, compares and moves), each counted
+# once -- a lower bound on their issue cost, so the peak step rate below is an
+# upper bound.
+OPS_PER_STEP = 172
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one full-rate VALU op per lane-cycle
 # (equals the published 78.6 TFLOP/s fp64 vector peak counted as FMA = 2).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
