@@ -303,7 +303,7 @@ def main():
     SOLVER = args.solver
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the simulation of one run "
-              "is not sharded across GPUs in this build", file=sys.stderr)
+              "is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
