@@ -878,10 +878,21 @@ __device__ __forceinline__ void load_node(const KParams& p, int k, Node<M>& s, i
 // exit, enter, internal transfer).  `counter`: the lane that counts them.
 // nrec holds the record at cur, loaded ahead so that days without events
 // wait for no memory access; for a wavefront-wide node (WIDE, cur and
-// wbase wave-uniform) the window of records from wbase (e1_window).
+// wbase wave-uniform) the window of records from wbase (e1_window).  A
+// wide node's cursor, stream and state are the same in every lane; read
+// from the first lane they are known to be uniform, so that the loop's
+// control and the sampling's integer work run on the scalar unit.
 template <class M, bool WIDE>
 __device__ __forceinline__ void day_events(const KParams& p, Node<M>& s, int b, double T, uint32_t stream, int& cur,
                                            int cend, int4& nrec, int& wbase, bool& dead, Tally& t, bool counter) {
+    if constexpr (WIDE) {
+        cur = __builtin_amdgcn_readfirstlane(cur);
+        cend = __builtin_amdgcn_readfirstlane(cend);
+        wbase = __builtin_amdgcn_readfirstlane(wbase);
+        stream = __builtin_amdgcn_readfirstlane(stream);
+#pragma unroll
+        for (int c = 0; c < M::NC; ++c) s.u[c] = __builtin_amdgcn_readfirstlane(s.u[c]);
+    }
     while (cur < cend) {
         const int4 rec = WIDE ? read_lane4(nrec, cur - wbase) : nrec;
         if (!((double)rec.x <= T)) break;
