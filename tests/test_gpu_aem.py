@@ -1,8 +1,10 @@
 """GPU parity of the all events method (section 3.4, solver 'aem') against
 the oracle's: every built-in model kind, scheduled events with and without
 external transfers in the free-running, barrier and dataflow kernels, a
-generated three-transition model, graph replay, and the first error.
-U must be bit-identical and the counters and error keys equal."""
+generated three-transition model, graph replay, the first error, and the
+full sizes the benchmark times (SIR with events, 10,000 nodes x 365 days,
+and the 4,096-run batch, both at their autotuned launch shapes).  U must be
+bit-identical and the counters and error keys equal."""
 import sys
 
 import numpy as np
@@ -123,3 +125,40 @@ def test_lane_queue_refused(lib):
     with pytest.raises(lib.SiminfError) as e:
         lib.Model(W.plain_sir(), solver="aem", lane_queue=1)
     assert e.value.code == -2
+
+
+def test_sir_events_full_size_autotuned(lib):
+    """SIR with scheduled events at full size (10,000 nodes x 365 days,
+    469,539 events) at the autotuned launch shape that the benchmark times:
+    U bit-exact and the counters equal."""
+    import oracle
+    spec = W.sir_with_events()
+    m = lib.Model(spec, solver="aem")
+    best = m.autotune(seed=3, repeats=1)
+    _say("autotuned", m.launch_info(), f"{best:.2f} ms")
+    m.run(61, 2)
+    rc = m.wait()
+    ref = oracle.run(spec, 61, 2, nthreads=16, solver="aem")
+    assert rc == 0 and ref["status"] == 0
+    _same(m, ref, "SIR with events, full size")
+
+
+def test_batch_full_size_sampled_runs(lib):
+    """The 4,096-run batch (64 parameter sets x 64 replicates, weekly sums)
+    as the benchmark runs it with the all events method, autotuned and
+    replayed from a captured graph: the weekly sums of sampled runs against
+    oracle runs of the same streams."""
+    import oracle
+    sets = W.ensemble_sets(seed=3, n_sets=64, replicates=64)
+    m = lib.Model([(s.spec, 64) for s in sets], record=lib.RECORD_SUMS, graph=1, solver="aem")
+    best = m.autotune(seed=7, repeats=1)
+    _say("batch autotuned", m.launch_info(), f"{best:.1f} ms")
+    m.run(83, 0)
+    assert m.wait() == 0, m.error_info()
+    sums = m.sums()
+    for run in (0, 2047, 2048, 4095):
+        spec = sets[run // 64].spec
+        _say("sampled run", run, spec.name, spec.Nn)
+        ref = oracle.run(spec, 83, run, nthreads=16, solver="aem")
+        assert ref["status"] == 0
+        assert np.array_equal(sums[run, :, :spec.Nc], ref["U"].astype(np.int64).sum(axis=1)), run
