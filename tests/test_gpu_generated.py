@@ -101,6 +101,22 @@ def test_vaccination_example(lib, mode):
     assert m.launch_info()["mode"] == mode
 
 
+def test_vaccination_full_size_autotuned(lib):
+    """The benchmark's vaccination workload (1,600 herds x 300 days, one
+    infected animal) at the launch shape the benchmark times (the
+    autotuner's pick): U and counters."""
+    spec = W.vaccination_example()
+    ref = _oracle(spec, 2026, 4)
+    m = lib.Model(spec)
+    best = m.autotune(seed=11, repeats=2)
+    _say("vaccination, autotuned", m.launch_info(), f"{best:.2f} ms")
+    m.run(2026, 4)
+    assert m.wait() == 0 and ref["status"] == 0
+    _check(m, ref, what=f"autotuned {m.launch_info()}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_age_structured_model(lib, mode):
     """Appendix B's age categories: six compartments and six transitions,

@@ -269,6 +269,21 @@ def test_sir_events_full_size(lib, mode):
     assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
 
 
+def test_sir_events_full_size_autotuned(lib):
+    """The benchmark workload at the launch shape the benchmark times (the
+    autotuner's pick): whole trajectory and counters."""
+    spec = W.sir_with_events()
+    ref = oracle_run(spec, 2025, 3)
+    m = lib.Model(spec)
+    best = m.autotune(seed=11, repeats=2)
+    _say("SIR with events, full size, autotuned", m.launch_info(), f"{best:.3f} ms")
+    m.run(2025, 3)
+    assert m.wait() == 0 and ref["status"] == 0
+    _compare(m, ref, what=f"autotuned {m.launch_info()}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+
+
 def test_autotune_keeps_bits(lib):
     spec = W.sir_with_events(seed=13, Nn=800, days=45)
     ref = oracle_run(spec, 77, 2)

@@ -199,3 +199,18 @@ def test_sise_sp_full_size(lib):
     assert m.wait() == 0
     _same(m, ref, what="SISe_sp full size")
     _counters_match(m, ref)
+
+
+def test_sise_sp_full_size_autotuned(lib):
+    """The full-size workload at the launch shape the benchmark times (the
+    autotuner's pick): whole trajectory, phi and counters."""
+    spec = W.sise_sp_with_events()
+    ref = _oracle(spec, 2017, 1)
+    assert ref["status"] == 0
+    m = lib.Model(spec)
+    best = m.autotune(seed=11, repeats=2)
+    _say("SISe_sp full size, autotuned", m.launch_info(), f"{best:.2f} ms")
+    m.run(2017, 1)
+    assert m.wait() == 0
+    _same(m, ref, what=f"autotuned {m.launch_info()}")
+    _counters_match(m, ref)
