@@ -99,6 +99,15 @@ def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
+def _per_node(a, n: int) -> np.ndarray:
+    """An (n, k) float64 view of per-node data given as (n, k) or flat;
+    with no nodes, k is the given array's second dimension (0 if flat)."""
+    a = np.asarray(a, dtype=np.float64)
+    if n == 0:
+        return a.reshape(0, a.shape[1] if a.ndim == 2 else 0)
+    return a.reshape(n, -1)
+
+
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
 
@@ -125,8 +134,8 @@ def run(spec, seed: int, stream: int = 0, nthreads: int | None = None, solver: s
     Nc, Nt = S.shape
     u0 = _c(spec.u0, np.int32)
     Nn = u0.shape[0]
-    v0 = _c(np.asarray(spec.v0, dtype=np.float64).reshape(Nn, -1), np.float64)
-    ldata = _c(np.asarray(spec.ldata, dtype=np.float64).reshape(Nn, -1), np.float64)
+    v0 = _c(_per_node(spec.v0, Nn), np.float64)
+    ldata = _c(_per_node(spec.ldata, Nn), np.float64)
     keep = dict(
         S=_c(S.ravel(order="F"), np.int32),
         G=_c(np.asarray(G).ravel(order="F"), np.int32),

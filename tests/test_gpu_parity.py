@@ -493,6 +493,66 @@ def test_automatic_packing(lib, case):
     _compare(m, ref, what=case)
 
 
+def _degenerate_spec(kind):
+    u0 = np.array([[90, 10, 0], [50, 5, 0], [0, 0, 0], [400, 3, 1]], np.int32)
+    if kind == "no_nodes":
+        return W.sir_spec(np.zeros((0, 3), np.int32), np.arange(0, 11, dtype=float))
+    if kind == "no_nodes_sise":
+        return W.sise_spec(np.zeros((0, 2), np.int32), np.arange(0, 5, dtype=float), 0.01, 0.1, 1.0,
+                           (0.1, 0.12, 0.1, 0.11))
+    if kind == "one_tspan":
+        return W.sir_spec(u0, np.array([0.0]))
+    if kind == "one_tspan_late":
+        return W.sir_spec(u0, np.array([7.0]))
+    return W.sir_spec(u0, np.arange(0, 21, dtype=float))
+
+
+@pytest.mark.parametrize("case", ["no_nodes", "no_nodes_sise", "one_tspan", "one_tspan_late"])
+def test_degenerate_sizes(lib, case):
+    """A model without nodes runs and records nothing; a single tspan point
+    records the initial state and simulates no day."""
+    spec = _degenerate_spec(case)
+    m, ref, rc = _run_both(lib, spec, 5, 1)
+    assert rc == 0 and ref["status"] == 0
+    c = m.counters()
+    assert (c["transitions"], c["node_days"], c["events"]) == (ref["transitions"], ref["node_days"], ref["events"])
+    if spec.Nn == 0:
+        U, V = m.trajectory()
+        assert U.size == 0 and V.size == 0 and c["node_days"] == 0
+    else:
+        _compare(m, ref, what=case)
+        assert np.array_equal(ref["U"][0], spec.u0)
+
+
+@pytest.mark.parametrize("lane_queue", [2, 1])
+def test_batch_with_an_empty_spec(lib, lane_queue):
+    """A ragged batch with a spec of no nodes between two others: every run
+    equals the oracle's run of its stream (full records without the lane
+    queue, weekly-style sums with it)."""
+    a = W.sir_with_events(seed=3, Nn=300, days=30)
+    a.events = W.empty_events()
+    b = W.sir_spec(np.array([[900, 100, 0], [30, 2, 0]], np.int32), a.tspan)
+    empty = W.sir_spec(np.zeros((0, 3), np.int32), a.tspan)
+    batch = [(a, 2), (empty, 2), (b, 3)]
+    record = lib.RECORD_FULL if lane_queue == 2 else lib.RECORD_SUMS
+    m = lib.Model(batch, record=record, lane_queue=lane_queue)
+    _say("batch with an empty spec", m.launch_info())
+    m.run(41, 9)
+    assert m.wait() == 0
+    specs = [a, a, empty, empty, b, b, b]
+    sums = m.sums() if record == lib.RECORD_SUMS else None
+    for r, spec in enumerate(specs):
+        ref = oracle_run(spec, 41, 9 + r)
+        if sums is not None:
+            want = ref["U"].astype(np.int64).sum(axis=1) if spec.Nn else np.zeros((len(spec.tspan), 3), np.int64)
+            assert np.array_equal(sums[r, :, :3], want), r
+        elif spec.Nn:
+            _compare(m, ref, run=r, what=f"batch run {r}")
+        else:
+            U, V = m.trajectory(r)
+            assert U.size == 0, r
+
+
 def test_split_run_equals_full_run(lib):
     """Draws are keyed by the absolute day: running [0, 40] and then
     [40, 90] from the saved state equals one run over [0, 90] on the GPU
