@@ -87,6 +87,32 @@ def test_sirs_three_transitions(lib):
     assert m.counters()["transitions"] == ref["transitions"]
 
 
+@pytest.mark.parametrize("solver", ["ssm", "aem"])
+def test_largest_model(lib, solver):
+    """A model at the limits of the model compiler: 16 compartments in a
+    chain and 32 transitions (a step forward and back between neighbours,
+    an immigration into the first and a death from the last), with rates
+    that read three global data; both solvers."""
+    comps = [f"C{i}" for i in range(16)]
+    tr = [f"C{i} -> a*C{i} -> C{i + 1}" for i in range(15)]
+    tr += [f"C{i + 1} -> b*C{i + 1}/(1+C{i}) -> C{i}" for i in range(15)]
+    tr += ["@ -> m -> C0", "C15 -> 0.05*C15 -> @"]
+    assert len(tr) == 32
+    rng = np.random.default_rng(9)
+    spec = W.mparse_spec(tr, comps, rng.integers(0, 40, size=(60, 16)), np.arange(0, 31),
+                         gdata=dict(a=0.3, b=0.2, m=2.5))
+    import oracle
+    ref = oracle.run(spec, 13, 4, nthreads=16, solver=solver)
+    m = lib.Model(spec, solver=solver)
+    _say("largest model", solver, m.launch_info())
+    m.run(13, 4)
+    assert m.wait() == 0 and ref["status"] == 0
+    _check(m, ref, what=f"16 x 32 model, {solver}")
+    c = m.counters()
+    assert (c["transitions"], c["node_days"]) == (ref["transitions"], ref["node_days"])
+    assert c["transitions"] > 10000
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_vaccination_example(lib, mode):
     """Section 5.1.2's example: five compartments (S, I, Icum, R, V), births,
