@@ -553,6 +553,39 @@ def test_batch_with_an_empty_spec(lib, lane_queue):
             assert U.size == 0, r
 
 
+def _event_edges_spec(rates):
+    """Events at their edge values on six nodes: proportions 0 and 1, a
+    fixed n equal to the selected total, proportions that round half up
+    (0.5 of 3, twice), events on nodes that an earlier event emptied, an
+    enter of n = 0, and an external transfer of a whole node."""
+    u0 = np.array([[5, 3, 2], [4, 4, 4], [7, 1, 0], [3, 1, 0], [10, 2, 1], [1, 1, 1]], np.int32)
+    E, X, IT, ET = W.ENTER, W.EXIT, W.INTTRANS, W.EXTTRANS
+    rows = [(X, 1, 0, 0, 0, 1.0, 3, -1), (X, 1, 1, 0, 0, 0.0, 3, -1), (X, 1, 2, 0, 8, 0.0, 3, -1),
+            (IT, 2, 3, 0, 0, 0.5, 0, 0), (ET, 2, 4, 5, 0, 1.0, 3, -1),
+            (X, 3, 5, 0, 0, 0.5, 1, -1), (X, 3, 0, 0, 0, 0.5, 3, -1), (E, 3, 1, 0, 0, 0.0, 0, -1),
+            (ET, 3, 2, 3, 0, 0.5, 3, 0), (IT, 4, 4, 0, 0, 1.0, 3, 0)]
+    beta, gamma = (0.16, 0.077) if rates else (0.0, 0.0)
+    spec = W.sir_spec(u0, np.arange(0, 7, dtype=float), beta, gamma, events=W.make_events(rows))
+    spec.N = np.array([[1], [1], [0]], np.int32)  # shift: S -> I, I -> R
+    return spec
+
+
+@pytest.mark.parametrize("rates", [False, True])
+@pytest.mark.parametrize("opts", [dict(mode=1), dict(mode=2, lanes=1), dict(mode=2, lanes=64, wide=6),
+                                  dict(mode=2, lanes=1, group=-1)])
+def test_event_edge_values(lib, rates, opts):
+    spec = _event_edges_spec(rates)
+    m, ref, rc = _run_both(lib, spec, 19, 3, **opts)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what=f"event edges {opts}")
+    c = m.counters()
+    assert (c["transitions"], c["events"]) == (ref["transitions"], ref["events"])
+    if not rates:
+        U = ref["U"]
+        assert U[1, 0].sum() == 0 and (U[1, 1] == [4, 4, 4]).all() and U[1, 2].sum() == 0
+        assert (U[2, 3] == [1, 3, 0]).all() and U[2, 4].sum() == 0 and (U[2, 5] == [11, 3, 2]).all()
+
+
 def test_split_run_equals_full_run(lib):
     """Draws are keyed by the absolute day: running [0, 40] and then
     [40, 90] from the saved state equals one run over [0, 90] on the GPU
