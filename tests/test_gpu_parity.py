@@ -586,6 +586,21 @@ def test_event_edge_values(lib, rates, opts):
         assert (U[2, 3] == [1, 3, 0]).all() and U[2, 4].sum() == 0 and (U[2, 5] == [11, 3, 2]).all()
 
 
+@pytest.mark.parametrize("rates", [False, True])
+@pytest.mark.parametrize("opts", [dict(lane_queue=1), dict(lane_queue=2), dict(lane_queue=2, lanes=64, wide=6)])
+def test_event_edge_values_free_running(lib, rates, opts):
+    """The same edge values without the external transfers, in the
+    free-running kernels (the lane queue, the lockstep kernel, wide nodes)."""
+    spec = _event_edges_spec(rates)
+    keep = spec.events["event"] != W.EXTTRANS
+    spec.events = {k: v[keep] for k, v in spec.events.items()}
+    m, ref, rc = _run_both(lib, spec, 23, 1, **opts)
+    assert rc == 0 and ref["status"] == 0
+    _compare(m, ref, what=f"event edges, free running {opts}")
+    c = m.counters()
+    assert (c["transitions"], c["events"]) == (ref["transitions"], ref["events"])
+
+
 def test_split_run_equals_full_run(lib):
     """Draws are keyed by the absolute day: running [0, 40] and then
     [40, 90] from the saved state equals one run over [0, 90] on the GPU
