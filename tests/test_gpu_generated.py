@@ -87,6 +87,31 @@ def test_sirs_three_transitions(lib):
     assert m.counters()["transitions"] == ref["transitions"]
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_event_edge_values(lib, mode):
+    """Scheduled events at their edge values on a generated SIR (the select
+    and shift tables compiled into the model): proportions 0 and 1, a fixed
+    n equal to the selected total, proportions that round half up, events on
+    emptied nodes, an enter of n = 0 and an external transfer of a whole
+    node."""
+    u0 = np.array([[5, 3, 2], [4, 4, 4], [7, 1, 0], [3, 1, 0], [10, 2, 1], [1, 1, 1]], np.int32)
+    E_, X, IT, ET = W.ENTER, W.EXIT, W.INTTRANS, W.EXTTRANS
+    rows = [(X, 1, 0, 0, 0, 1.0, 3, -1), (X, 1, 1, 0, 0, 0.0, 3, -1), (X, 1, 2, 0, 8, 0.0, 3, -1),
+            (IT, 2, 3, 0, 0, 0.5, 0, 0), (ET, 2, 4, 5, 0, 1.0, 3, -1),
+            (X, 3, 5, 0, 0, 0.5, 1, -1), (X, 3, 0, 0, 0, 0.5, 3, -1), (E_, 3, 1, 0, 0, 0.0, 0, -1),
+            (ET, 3, 2, 3, 0, 0.5, 3, 0), (IT, 4, 4, 0, 0, 1.0, 3, 0)]
+    E = np.array([[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 1]], np.int32)
+    N = np.array([[1], [1], [0]], np.int32)
+    # (1 + S + I + R: the emptied nodes would make S*I/(S+I+R) 0/0, an error)
+    spec = W.mparse_spec(["S -> b*S*I/(1+S+I+R) -> I", "I -> g*I -> R"], ["S", "I", "R"], u0,
+                         np.arange(0, 7), gdata=dict(b=0.16, g=0.077), E=E, N=N, events=W.make_events(rows))
+    m, ref, rc = _run(lib, spec, 19, 3, mode=mode)
+    assert rc == 0 and ref["status"] == 0
+    _check(m, ref, what=f"event edges, generated, mode {mode}")
+    c = m.counters()
+    assert (c["transitions"], c["events"]) == (ref["transitions"], ref["events"])
+
+
 @pytest.mark.parametrize("solver", ["ssm", "aem"])
 def test_largest_model(lib, solver):
     """A model at the limits of the model compiler: 16 compartments in a
