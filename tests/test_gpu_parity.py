@@ -601,6 +601,20 @@ def test_event_edge_values_free_running(lib, rates, opts):
     assert (c["transitions"], c["events"]) == (ref["transitions"], ref["events"])
 
 
+@pytest.mark.parametrize("opts", [dict(mode=1), dict(mode=2)])
+def test_event_edge_values_all_events_method(lib, opts):
+    """The edge values with the all events method (one lane per node)."""
+    import oracle
+    spec = _event_edges_spec(True)
+    ref = oracle.run(spec, 29, 2, nthreads=NTHREADS, solver="aem")
+    m = lib.Model(spec, solver="aem", **opts)
+    m.run(29, 2)
+    assert m.wait() == 0 and ref["status"] == 0
+    _compare(m, ref, what=f"event edges, aem {opts}")
+    c = m.counters()
+    assert (c["transitions"], c["events"]) == (ref["transitions"], ref["events"])
+
+
 def test_split_run_equals_full_run(lib):
     """Draws are keyed by the absolute day: running [0, 40] and then
     [40, 90] from the saved state equals one run over [0, 90] on the GPU
