@@ -214,3 +214,19 @@ def test_sise_sp_full_size_autotuned(lib):
     assert m.wait() == 0
     _same(m, ref, what=f"autotuned {m.launch_info()}")
     _counters_match(m, ref)
+
+
+@pytest.mark.parametrize("Nn,days", [(400, 150), (1600, 1460)])
+def test_sise_sp_all_events_method(lib, Nn, days):
+    """The coupled post-time step under the all events method (one lane per
+    node, the dataflow kernel): U and phi bit-identical, counters equal."""
+    import oracle
+    spec = W.sise_sp_with_events(seed=5, Nn=Nn, days=days)
+    ref = oracle.run(spec, 17, 2, nthreads=NTHREADS, solver="aem")
+    assert ref["status"] == 0
+    m = lib.Model(spec, solver="aem")
+    _say("SISe_sp, all events method", Nn, days, m.launch_info())
+    m.run(17, 2)
+    assert m.wait() == 0
+    _same(m, ref, what=f"SISe_sp aem {Nn} x {days}")
+    _counters_match(m, ref)
